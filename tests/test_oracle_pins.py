@@ -1,0 +1,302 @@
+"""Pins for the FP64 CPU oracle: each part is checked against something other than
+itself -- closed forms, an independent definition, dense LAPACK diagonalisation
+or brute force on tiny inputs."""
+import numpy as np
+import pytest
+
+import oracle as O
+from topi import csr_to_dense, diag_csr, random_phase_block, topi_csr
+from tests.bloch import bloch_spectrum
+
+
+# --------------------------------------------------------------------------- coefficients
+def _cheb_quadrature(f, n_p, N=400000):
+    """(2 - delta_p0)/pi int_0^pi f(cos t) cos(pt) dt by the midpoint rule in t."""
+    t = np.pi * (np.arange(N) + 0.5) / N
+    ft = f(np.cos(t))
+    p = np.arange(n_p + 1)
+    c = np.array([np.mean(ft * np.cos(k * t)) for k in p]) * 2.0
+    c[0] /= 2.0
+    return c
+
+
+@pytest.mark.parametrize("a,b", [(-0.3, 0.2), (-0.05, 0.05), (0.1, 0.9), (-0.99, -0.5)])
+def test_window_coefficients_match_quadrature(a, b):
+    c = O.window_coefficients(a, b, 60)
+    q = _cheb_quadrature(lambda x: ((x >= a) & (x <= b)).astype(float), 60)
+    assert np.max(np.abs(c - q)) < 2e-5
+
+
+def test_window_symmetric_interval_odd_terms_vanish():
+    c = O.window_coefficients(-0.2, 0.2, 101)
+    assert np.max(np.abs(c[1::2])) < 1e-15
+    assert abs(c[0] - (np.arccos(-0.2) - np.arccos(0.2)) / np.pi) < 1e-15
+
+
+def test_jackson_equals_autocorrelation_of_sine_sequence():
+    # independent definition: g_p = sum_v a_v a_{v+p} for the unit-norm a_v ~ sin(pi (v+1)/(M+1))
+    for n_p in (5, 40, 199):
+        M = n_p + 1
+        a = np.sin(np.pi * (np.arange(M) + 1) / (M + 1))
+        a /= np.linalg.norm(a)
+        ac = np.array([np.dot(a[:M - p], a[p:]) for p in range(M)])
+        assert np.max(np.abs(O.jackson_damping(n_p) - ac)) < 1e-14
+
+
+def test_jackson_properties():
+    g = O.jackson_damping(200)
+    assert g[0] == pytest.approx(1.0, abs=1e-15)
+    assert np.all(g > 0) and np.all(np.diff(g) < 0)
+
+
+@pytest.mark.parametrize("a,b,n_p", [(-0.1, 0.1, 200), (-0.4, 0.3, 57), (0.5, 0.95, 400)])
+def test_damped_window_polynomial_between_0_and_1(a, b, n_p):
+    # Jackson damping keeps the polynomial approximation of an indicator in [0, 1]
+    gam = O.jackson_damping(n_p) * O.window_coefficients(a, b, n_p)
+    x = np.linspace(-1, 1, 100001)
+    pv = np.cos(np.outer(np.arccos(x), np.arange(n_p + 1))) @ gam
+    assert pv.min() > -1e-12 and pv.max() < 1 + 1e-12
+
+
+def test_damped_window_converges_to_indicator():
+    a, b = -0.2, 0.3
+    inside, outside = 0.05, 0.6
+    prev_in, prev_out = 0.0, 1.0
+    for n_p in (50, 200, 800):
+        gam = O.jackson_damping(n_p) * O.window_coefficients(a, b, n_p)
+        pv = np.cos(np.outer(np.arccos([inside, outside]), np.arange(n_p + 1))) @ gam
+        assert pv[0] > prev_in - 1e-12 and pv[1] < prev_out + 1e-12
+        prev_in, prev_out = pv
+    assert prev_in > 0.999 and prev_out < 1e-6
+
+
+# --------------------------------------------------------------------------- scaling
+def test_gershgorin_brute_force_and_contains_spectrum():
+    H = topi_csr(3, 4, 3, m=1.2, W=2.5, seed=8, dilution=0.2, dilution_seed=1)
+    A = csr_to_dense(*H)
+    c = np.real(np.diag(A))
+    r = np.sum(np.abs(A), axis=1) - np.abs(np.diag(A))
+    lo, hi = O.gershgorin_bounds(H)
+    assert lo == pytest.approx(np.min(c - r), abs=1e-13)
+    assert hi == pytest.approx(np.max(c + r), abs=1e-13)
+    e = np.linalg.eigvalsh(A)
+    assert lo <= e[0] and e[-1] <= hi
+
+
+def test_gershgorin_topi_closed_form():
+    from topi import site_disorder
+    m, W, t = 1.0, 1.0, 1.0
+    H = topi_csr(4, 4, 4, m=m, W=W, t=t, seed=5)
+    lo, hi = O.gershgorin_bounds(H)
+    V = site_disorder(64, W, 5)
+    assert hi == pytest.approx(np.max(np.abs(m + V)) + 6 * t, abs=1e-14)
+    assert lo == -hi
+    alpha, beta = O.scale_factors(lo, hi)
+    assert beta == 0.0 and alpha * hi == pytest.approx(1.0, abs=1e-15)
+
+
+def test_scale_factors_map_to_unit_interval():
+    al, be = O.scale_factors(-3.0, 5.0)
+    assert al * -3.0 + be == pytest.approx(-1.0) and al * 5.0 + be == pytest.approx(1.0)
+    with pytest.raises(ValueError):
+        O.scale_factors(1.0, 1.0)
+
+
+# --------------------------------------------------------------------------- filter (Alg. 1/2)
+@pytest.mark.parametrize("n_s,n_b,n_p", [(4, 2, 50), (6, 6, 3), (3, 1, 2), (2, 2, 1), (2, 1, 0)])
+def test_filter_chebyshev_identity(n_s, n_b, n_p):
+    # H = diag(cos t_j), alpha = 1, beta = 0:  T_p(H) x = cos(p t) x exactly
+    n = 300
+    t = np.linspace(0.003, np.pi - 0.003, n)
+    H = diag_csr(np.cos(t))
+    gam = np.random.default_rng(n_p).standard_normal(n_p + 1)
+    X = random_phase_block(n, n_s, 1)
+    Y, eta, nu = O.chebyshev_filter(H, 1.0, 0.0, gam, X, n_b)
+    P = np.arange(n_p + 1)
+    C = np.cos(np.outer(t, P))               # C[i, p] = cos(p t_i) = T_p(cos t_i)
+    assert np.max(np.abs(Y - (C @ gam)[:, None] * X)) < 1e-12 * max(1, n_p)
+    w = np.abs(X) ** 2
+    for p in range(1, n_p + 1):
+        assert np.allclose(eta[p], (C[:, p] * C[:, p - 1]) @ w, atol=1e-11)
+        assert np.allclose(nu[p], (C[:, p - 1] ** 2) @ w, atol=1e-11)
+
+
+@pytest.mark.parametrize("dims,W,n_b", [((4, 4, 3), 2.0, 4), ((3, 3, 4), 0.5, 8)])
+def test_filter_equals_dense_polynomial(dims, W, n_b):
+    # p(H~) X through the eigendecomposition: an independent evaluation of the filter
+    H = topi_csr(*dims, m=1.0, W=W, seed=4)
+    A = csr_to_dense(*H)
+    lo, hi = O.gershgorin_bounds(H)
+    al, be = O.scale_factors(lo, hi)
+    gam = O.filter_coefficients(-0.4, 0.25, al, be, 90)
+    X = random_phase_block(A.shape[0], 8, 5)
+    Y, eta, nu = O.chebyshev_filter(H, al, be, gam, X, n_b)
+    L, V = np.linalg.eigh(A)
+    pl = np.cos(np.outer(np.arccos(np.clip(al * L + be, -1, 1)), np.arange(91))) @ gam
+    Yd = V @ (pl[:, None] * (V.conj().T @ X))
+    assert np.max(np.abs(Y - Yd)) < 1e-12
+
+
+def test_moments_equal_dense_spectral_sums():
+    H = topi_csr(4, 3, 3, m=1.0, W=1.0, seed=6)
+    A = csr_to_dense(*H)
+    lo, hi = O.gershgorin_bounds(H)
+    al, be = O.scale_factors(lo, hi)
+    n_p = 64
+    X = random_phase_block(A.shape[0], 4, 7)
+    _, eta, nu = O.chebyshev_filter(H, al, be, np.ones(n_p + 1), X, 4)
+    mu = O.kpm_moments(eta, nu)
+    L, V = np.linalg.eigh(A)
+    w = np.abs(V.conj().T @ X) ** 2
+    ref = np.cos(np.outer(np.arange(2 * n_p), np.arccos(al * L + be))) @ w
+    assert np.max(np.abs(mu - ref)) < 1e-11
+    assert np.max(np.abs(mu.imag)) < 1e-11
+
+
+def test_moments_odd_trace_vanishes_for_chiral_matrix():
+    # trace moments (all unit vectors) of the chiral Topi matrix: odd ones are zero
+    H = topi_csr(3, 3, 3, m=1.0, W=1.0, seed=2)
+    n = 108
+    lo, hi = O.gershgorin_bounds(H)
+    al, be = O.scale_factors(lo, hi)
+    _, eta, nu = O.chebyshev_filter(H, al, be, np.ones(21), np.eye(n), 36)
+    mu = O.kpm_moments(eta, nu).sum(axis=1)
+    assert abs(mu[0] - n) < 1e-12
+    assert np.max(np.abs(mu[1::2])) < 1e-10
+
+
+def test_count_estimate_close_to_exact_count():
+    H = topi_csr(6, 6, 6, m=1.0, W=1.0, seed=21)
+    A = csr_to_dense(*H)
+    n = A.shape[0]
+    lo, hi = O.gershgorin_bounds(H)
+    al, be = O.scale_factors(lo, hi)
+    lam_L, lam_R = -1.0, 1.0
+    e = np.linalg.eigvalsh(A)
+    exact = np.count_nonzero((e >= lam_L) & (e <= lam_R))
+    n_p, R = 200, 16
+    X = random_phase_block(n, R, 99)
+    _, eta, nu = O.chebyshev_filter(H, al, be, np.ones(n_p + 1), X, 16)
+    est = O.count_estimate(O.kpm_moments(eta, nu), n, al * lam_L + be, al * lam_R + be)
+    # stochastic trace error ~ sqrt(count / R); plus the smoothing at the window edges
+    assert abs(est - exact) < 4 * np.sqrt(exact / R) + 3
+
+
+# --------------------------------------------------------------------------- SVQB / RR / residuals
+def test_svqb_orthonormal_same_span():
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((400, 12)) + 1j * rng.standard_normal((400, 12))
+    Y[:, 5] *= 1e-6
+    Q, nd = O.svqb(Y)
+    assert nd == 0
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(12))) < 1e-9
+    Q2, _ = O.svqb(Q)
+    assert np.max(np.abs(Q2.conj().T @ Q2 - np.eye(12))) < 1e-14
+    P1 = Q2 @ Q2.conj().T
+    Qy, _ = np.linalg.qr(Y)
+    assert np.max(np.abs(P1 - Qy @ Qy.conj().T)) < 1e-10
+
+
+def test_svqb_drops_dependent_columns():
+    rng = np.random.default_rng(4)
+    Y = rng.standard_normal((300, 8)) + 1j * rng.standard_normal((300, 8))
+    Y[:, 3] = Y[:, 1]
+    Y[:, 6] = 2 * Y[:, 0] - Y[:, 2]
+    Q, nd = O.svqb(Y)
+    assert nd == 2 and Q.shape == (300, 6)
+    Q, nd = O.svqb(Q)
+    assert nd == 0
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(6))) < 1e-13
+    # the kept directions still span the original columns
+    assert np.max(np.abs(Y - Q @ (Q.conj().T @ Y))) < 1e-10
+
+
+def test_rayleigh_ritz_on_exact_invariant_subspace():
+    H = topi_csr(4, 3, 3, m=1.0, W=2.0, seed=12)
+    A = csr_to_dense(*H)
+    L, V = np.linalg.eigh(A)
+    idx = [10, 40, 41, 77]
+    rng = np.random.default_rng(0)
+    M, _ = np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))
+    theta, Z = O.rayleigh_ritz(H, V[:, idx] @ M)
+    assert np.max(np.abs(theta - L[idx])) < 1e-12
+    r = O.residual_norms(H, Z, theta)
+    assert np.max(r) < 1e-12
+
+
+def test_residual_norms_brute_force():
+    H = topi_csr(3, 3, 3, m=1.0, W=1.0, seed=1)
+    A = csr_to_dense(*H)
+    Z = random_phase_block(108, 3, 3)
+    th = np.array([0.1, -0.5, 2.0])
+    r = O.residual_norms(H, Z, th)
+    Zn = Z / np.linalg.norm(Z, axis=0)
+    assert np.allclose(r, np.linalg.norm(A @ Zn - Zn * th, axis=0), rtol=1e-13)
+
+
+def test_fix_phases():
+    Z = random_phase_block(50, 3, 1) * np.array([1.0, 2.0, 3.0])
+    Z[7, 1] = 10j
+    F = O.fix_phases(Z)
+    assert np.allclose(np.abs(F), np.abs(Z))
+    assert F[7, 1] == pytest.approx(10.0)
+
+
+# --------------------------------------------------------------------------- full solve
+@pytest.mark.parametrize("dims,W,interval,n_s,n_p,n_b", [
+    ((4, 4, 3), 2.0, (-0.8, 0.8), 32, 150, 16),
+    ((6, 6, 4), 1.0, (-0.35, 0.35), 32, 200, 32),
+])
+def test_solve_matches_lapack(dims, W, interval, n_s, n_p, n_b):
+    H = topi_csr(*dims, m=1.0, W=W, seed=1001)
+    A = csr_to_dense(*H)
+    n = A.shape[0]
+    e = np.linalg.eigvalsh(A)
+    lam_L, lam_R = interval
+    ref = e[(e >= lam_L) & (e <= lam_R)]
+    res = O.chebfd_solve(H, lam_L, lam_R, n_s, n_p, n_b, random_phase_block(n, n_s, 43),
+                         refill_seed=44)
+    assert res.status == 0
+    assert res.n_found == len(ref) and len(ref) % 2 == 0
+    assert np.max(np.abs(np.sort(res.theta[:res.n_found]) - ref)) < 1e-12
+    assert np.max(res.resid[:res.n_found]) <= 1e-9
+    # residuals recomputed independently from the returned vectors
+    Z = res.Z[:, :res.n_found]
+    Zn = Z / np.linalg.norm(Z, axis=0)
+    assert np.max(np.linalg.norm(A @ Zn - Zn * res.theta[:res.n_found], axis=0)) <= 1e-9
+
+
+def test_solve_clean_lattice_matches_bloch():
+    # clean 16x16x8 lattice (the small configuration's shape), m = t = 1: twelve
+    # zero modes, next level |E| ~ 0.39; completeness from the closed form
+    dims = (16, 16, 8)
+    H = topi_csr(*dims, m=1.0, W=0.0)
+    n = 4 * 16 * 16 * 8
+    E = bloch_spectrum(*dims, 1.0)
+    ref = E[(E >= -0.05) & (E <= 0.05)]
+    assert len(ref) == 12
+    res = O.chebfd_solve(H, -0.05, 0.05, 32, 200, 32, random_phase_block(n, 32, 43),
+                         refill_seed=44)
+    assert res.status == 0 and res.n_found == 12
+    assert np.max(np.abs(res.theta[:12] - ref)) < 1e-12
+    assert np.max(res.resid[:12]) <= 1e-9
+
+
+def test_solve_small_configuration_matches_shift_invert():
+    # Topi-16-16-8, m = W = 1, interval [-0.05, 0.05] in H's units, n_s = n_b = 32,
+    # n_p = 200: the eigenvalues nearest 0 from sparse shift-invert Lanczos (ARPACK
+    # with a sparse LU), an independent method
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    dims = (16, 16, 8)
+    n = 4 * 16 * 16 * 8
+    H = topi_csr(*dims, m=1.0, W=1.0, seed=1001)
+    A = sp.csr_matrix((H[2], H[1], H[0]), shape=(n, n)).tocsc()
+    near0 = np.sort(sla.eigsh(A, k=24, sigma=0.0, which="LM", return_eigenvectors=False))
+    ref = near0[np.abs(near0) <= 0.05]
+    assert np.abs(near0).max() > 0.05          # the 24 nearest include everything inside
+    res = O.chebfd_solve(H, -0.05, 0.05, 32, 200, 32, random_phase_block(n, 32, 43),
+                         refill_seed=44)
+    assert res.status == 0 and res.n_found == len(ref)
+    assert np.max(np.abs(res.theta[:res.n_found] - ref)) < 1e-12
+    assert np.max(res.resid[:res.n_found]) <= 1e-9
