@@ -1,0 +1,187 @@
+/*
+ * chebfd.h -- C ABI of libchebfd, a single-GPU (AMD MI355X, gfx950) library for
+ * Chebyshev filter diagonalization (ChebFD) of large sparse Hermitian matrices.
+ *
+ * Method: Kreutzer, Hager, Ernst, Fehske, Bishop, Wellein, "Chebyshev Filter
+ * Diagonalization on Modern Manycore Processors and GPGPUs" (arXiv:1803.02156).
+ * ChebFD projects n_s search vectors onto the eigenvectors whose eigenvalues lie
+ * in a search interval, using a polynomial window filter of degree n_p in the
+ * scaled matrix alpha*H + beta*I (Sect. 2, Alg. 1), applied to blocks of n_b
+ * vectors in turn (Sect. 3.3, Alg. 2).
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are device (HIP) memory, h_* are host memory.  The
+ *    library never allocates device memory: the caller passes buffers and the
+ *    byte sizes it was told by the matching *_query call.  Host arrays are only
+ *    read (or written, for outputs) during the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *    enqueued on it; a call returns before the work finishes unless stated.
+ *  - Complex numbers are interleaved (re, im) pairs: c128 = 2 doubles,
+ *    c64 = 2 floats.
+ *  - Return value: 0 on success, > 0 a warning with valid outputs, < 0 an error
+ *    (outputs untouched, nothing enqueued).  chebfd_last_error() gives a
+ *    thread-local message for the last failing call.  No C++ exception crosses
+ *    the interface.  All arguments are validated before the first launch.
+ */
+#ifndef CHEBFD_H
+#define CHEBFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CHEBFD_OK               0
+#define CHEBFD_NOT_CONVERGED    1   /* max_iter reached; outputs hold the last iterate */
+#define CHEBFD_SUBSPACE_SMALL   2   /* more than 3/4 n_s Ritz values in the interval */
+#define CHEBFD_EINVAL         (-1)  /* invalid argument (sizes, NULL, alignment, aliasing) */
+#define CHEBFD_EHIP           (-2)  /* a HIP runtime call failed */
+#define CHEBFD_EWORKSPACE     (-3)  /* caller buffer smaller than the queried size */
+#define CHEBFD_EINTERVAL      (-4)  /* search interval not strictly inside the spectral bounds */
+#define CHEBFD_ENUMERIC       (-5)  /* non-finite value or failed small eigensolve */
+
+/* ---- precision of the block vectors and matrix values ------------------- */
+#define CHEBFD_PREC_FP64   0   /* c128 vectors and matrix, FP64 arithmetic */
+#define CHEBFD_PREC_MIXED  1   /* c64 vectors and matrix, FP32 sparse products, FP64 dot products */
+
+/*
+ * Device-resident sparse matrix in SELL-C-sigma format.  Rows are grouped in
+ * chunks of C consecutive rows; within windows of sigma rows, rows are sorted by
+ * decreasing length (stable, ties keep the original order), which is a
+ * symmetric permutation P H P^T; each chunk is padded to its longest row and
+ * stored column-major (slot k of the chunk's rows is contiguous).  Padding slots
+ * hold value 0 and the row's own index.  Column indices are in permuted
+ * numbering; all block vectors handled by the filter calls are in permuted row
+ * order too (chebfd_pack/unpack convert).  This is a plain-old-data handle:
+ * its pointers point into the d_buf given to chebfd_matrix_build, which the
+ * caller owns and must keep alive.
+ */
+typedef struct chebfd_matrix {
+    int64_t n;                  /* dimension */
+    int64_t nnz;                /* stored entries of the input CRS matrix */
+    int64_t n_chunks;           /* ceil(n / C) */
+    int64_t slots;              /* stored slots including padding */
+    int32_t C;                  /* chunk height */
+    int32_t sigma;              /* sorting window (multiple of C, or 1) */
+    int32_t prec;               /* CHEBFD_PREC_* of the stored values */
+    int32_t max_width;          /* longest row */
+    int32_t identity_perm;      /* 1 if the permutation is the identity */
+    int32_t reserved;
+    const int64_t *chunk_off;   /* [n_chunks + 1] first slot of each chunk */
+    const int32_t *chunk_width; /* [n_chunks] slots per row in the chunk */
+    const int32_t *col;         /* [slots] permuted column index */
+    const void *val;            /* [slots] complex values (c128 or c64 per prec) */
+    const int32_t *perm;        /* [n] perm[new] = old row */
+    const int32_t *iperm;       /* [n] iperm[old] = new row */
+} chebfd_matrix;
+
+/* Version of the ABI (major*10000 + minor*100 + patch). */
+int chebfd_version(void);
+
+/* Message describing the last failing call on this thread ("" if none). */
+const char *chebfd_last_error(void);
+
+/* Device properties the launchers use: number of compute units and the name. */
+int chebfd_device_info(int32_t *num_cus, char *name, int32_t name_len);
+
+/*
+ * Matrix ingest (the paper's CRS format, Sect. 3.1: 4-byte column indices,
+ * complex double values) into SELL-C-sigma.
+ * chebfd_matrix_query: bytes of device memory chebfd_matrix_build needs.
+ * chebfd_matrix_build: builds the format on the host, copies it into d_buf on
+ *   `stream` and synchronises that stream before returning (setup, once).
+ *   h_rowptr[n+1] (int64, h_rowptr[0] = 0, non-decreasing), h_col[nnz] in [0, n),
+ *   h_val[2*nnz] interleaved c128.  The matrix must be Hermitian (not checked).
+ *   C in {1..1024}, sigma >= 1 and a multiple of C (or 1); prec per CHEBFD_PREC_*.
+ *   d_buf must be 256-byte aligned.
+ */
+int chebfd_matrix_query(int64_t n, const int64_t *h_rowptr, int32_t C, int32_t sigma,
+                        int32_t prec, size_t *bytes);
+int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col,
+                        const double *h_val, int32_t C, int32_t sigma, int32_t prec,
+                        void *d_buf, size_t bytes, void *stream, chebfd_matrix *out);
+
+/*
+ * Gershgorin bounds of H (the interval that must be mapped onto [-1, 1] by the
+ * scaling alpha*H + beta*I of Alg. 1): lam_lo = min_i (Re H_ii - r_i),
+ * lam_hi = max_i (Re H_ii + r_i), r_i = sum_{j != i} |H_ij|.  Computed on the
+ * device; d_work of chebfd_bounds_query bytes; synchronises `stream`.
+ */
+int chebfd_bounds_query(const chebfd_matrix *H, size_t *work_bytes);
+int chebfd_bounds(const chebfd_matrix *H, void *d_work, size_t work_bytes, void *stream,
+                  double *lam_lo, double *lam_hi);
+
+/*
+ * Filter coefficients (host): gamma_p = g_p c_p, p = 0..n_p, where c_p are the
+ * Chebyshev coefficients of the indicator of the scaled interval
+ * [a, b] = [alpha lam_L + beta, alpha lam_R + beta] (the window function of
+ * Sect. 2) and g_p the Jackson damping factors for n_p + 1 terms (Alg. 1,
+ * lines 6 and 12 use the products g_p c_p).  Also returns alpha, beta from
+ * the bounds [lam_lo, lam_hi].  CHEBFD_EINTERVAL unless -1 < a < b < 1.
+ */
+int chebfd_coefficients(double lam_lo, double lam_hi, double lam_L, double lam_R,
+                        int32_t n_p, double *alpha, double *beta, double *h_gamma);
+
+/*
+ * Layout conversion between the user's column-major c128 block (n x m, ld = n,
+ * original row order) and the filter's blocked layout (Fig. 3 of Sect. 3.3):
+ * m/n_b blocks of n_b vectors, each block an n x n_b row-major array (the n_b
+ * entries of a row contiguous), blocks stored one after another, rows in the
+ * matrix's permuted order, elements c128 (prec FP64) or c64 (prec MIXED).
+ * m % n_b == 0.  d_src and d_dst must not overlap.
+ */
+int chebfd_pack(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec,
+                const void *d_colmajor, void *d_blocked, void *stream);
+int chebfd_unpack(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec,
+                  const void *d_blocked, void *d_colmajor, void *stream);
+
+/*
+ * The polynomial filter (Alg. 1 on each block, Alg. 2 over the blocks):
+ * d_xy (blocked layout, n_s vectors, precision `prec`) holds X on entry and
+ * Y = sum_{p=0}^{n_p} gamma_p T_p(alpha H + beta I) X on return (the paper
+ * overwrites X by the filtered block).  Each step p >= 3 is one launch of the
+ * fused kernel (chebfd_op: recurrence W <- 2(alpha H + beta I) U - W, the dot
+ * products eta_p = <W, U>, mu_p = <U, U> and X <- X + gamma_p W in one pass).
+ * d_u, d_w: n x n_b work blocks of the same precision.
+ * d_eta: (n_p + 1) x n_s c128 and d_nu: (n_p + 1) x n_s FP64 (entry p*n_s + j,
+ * column j in 0..n_s-1), receiving for p = 1..n_p
+ *   eta[p] = <T_p x, T_{p-1} x>,  nu[p] = <T_{p-1} x, T_{p-1} x>
+ * (with <a, b> = sum_i conj(a_i) b_i, FP64 accumulation, deterministic
+ * summation order); row 0 is not written.  May be NULL together (moments not
+ * needed is not faster: they are computed in the same pass).
+ * d_work: chebfd_filter_query bytes.  n_b in {1,2,4,8,16,32,64,128},
+ * n_s % n_b == 0, n_p >= 0, gamma[n_p + 1] on the host.
+ * Buffers must be 256-byte aligned and must not overlap.
+ */
+int chebfd_filter_query(const chebfd_matrix *H, int32_t n_b, size_t *work_bytes);
+int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
+                  int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
+                  void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,
+                  void *stream);
+
+/*
+ * One fused Chebyshev step on one block, as timed by the benchmarks (Alg. 1,
+ * lines 9-12): W <- 2(alpha H + beta I) U - W in place, eta_p = <W, U>,
+ * mu_p = <U, U>, Y <- Y + gamma W.  Same layouts and workspace as
+ * chebfd_filter; the dot products stay in d_work (not reduced).
+ */
+int chebfd_op(const chebfd_matrix *H, double alpha, double beta, double gamma, int32_t n_b,
+              int32_t prec, const void *d_u, void *d_w, void *d_y, void *d_work,
+              size_t work_bytes, void *stream);
+
+/*
+ * HBM bandwidth probe (the STREAM analogue of Sect. 1.2, Table 2): copy
+ * (b = a) or triad (a = b + s c) over `count` doubles.  kind 0 = copy,
+ * kind 1 = triad.
+ */
+int chebfd_probe_stream(int32_t kind, int64_t count, const double *d_b, const double *d_c,
+                        double s, double *d_a, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEBFD_H */

@@ -1,0 +1,584 @@
+// C ABI of libchebfd: argument validation, SELL-C-sigma ingest on the host,
+// the filter driver (Alg. 1 per block, Alg. 2 over blocks) and small helpers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace chebfd {
+
+static thread_local std::string g_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+}
+
+void clear_error() { g_error.clear(); }
+
+int device_props(DeviceProps *out) {
+    static std::mutex mu;
+    static DeviceProps cache[64];
+    static bool have[64] = {};
+    int dev = 0;
+    CHEBFD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) CHEBFD_FAIL(CHEBFD_EHIP, "device id %d out of range", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!have[dev]) {
+        hipDeviceProp_t p;
+        CHEBFD_HIP(hipGetDeviceProperties(&p, dev));
+        DeviceProps &d = cache[dev];
+        d.id = dev;
+        d.num_cus = p.multiProcessorCount;
+        d.max_threads_per_cu = p.maxThreadsPerMultiProcessor;
+        snprintf(d.name, sizeof(d.name), "%s", p.gcnArchName);
+        have[dev] = true;
+    }
+    *out = cache[dev];
+    return CHEBFD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// SELL-C-sigma layout on the host
+// ---------------------------------------------------------------------------
+struct SellPlan {
+    int64_t n = 0, n_chunks = 0, slots = 0;
+    int32_t max_width = 0;
+    bool identity = true;
+    std::vector<int32_t> perm;         // new -> old
+    std::vector<int32_t> width;        // per chunk
+    std::vector<int64_t> off;          // per chunk + 1
+};
+
+static int ilog2_exact(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return (1 << l) == v ? l : -1;
+}
+
+static int check_matrix_args(int64_t n, const int64_t *rowptr, int32_t C, int32_t sigma,
+                             int32_t prec) {
+    CHEBFD_REQUIRE(n >= 1 && n < (int64_t(1) << 31), "n = %lld out of range [1, 2^31)", (long long)n);
+    CHEBFD_REQUIRE(rowptr != nullptr, "h_rowptr is NULL");
+    CHEBFD_REQUIRE(C >= 1 && C <= 1024 && ilog2_exact(C) >= 0, "C = %d must be a power of two in [1, 1024]", C);
+    CHEBFD_REQUIRE(sigma == 1 || (sigma >= C && sigma % C == 0), "sigma = %d must be 1 or a multiple of C", sigma);
+    CHEBFD_REQUIRE(prec == CHEBFD_PREC_FP64 || prec == CHEBFD_PREC_MIXED, "prec = %d invalid", prec);
+    CHEBFD_REQUIRE(rowptr[0] == 0, "h_rowptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+        CHEBFD_REQUIRE(rowptr[i + 1] >= rowptr[i], "h_rowptr decreases at row %lld", (long long)i);
+    return CHEBFD_OK;
+}
+
+static void make_plan(int64_t n, const int64_t *rowptr, int32_t C, int32_t sigma, SellPlan &p) {
+    p.n = n;
+    p.perm.resize(n);
+    std::iota(p.perm.begin(), p.perm.end(), 0);
+    auto len = [&](int32_t r) { return rowptr[r + 1] - rowptr[r]; };
+    if (sigma > 1) {
+        for (int64_t w0 = 0; w0 < n; w0 += sigma) {
+            const int64_t w1 = std::min<int64_t>(n, w0 + sigma);
+            std::stable_sort(p.perm.begin() + w0, p.perm.begin() + w1,
+                             [&](int32_t a, int32_t b) { return len(a) > len(b); });
+        }
+    }
+    p.identity = true;
+    for (int64_t i = 0; i < n; ++i)
+        if (p.perm[i] != i) { p.identity = false; break; }
+    p.n_chunks = (n + C - 1) / C;
+    p.width.assign(p.n_chunks, 0);
+    p.off.assign(p.n_chunks + 1, 0);
+    p.max_width = 0;
+    for (int64_t c = 0; c < p.n_chunks; ++c) {
+        int64_t w = 0;
+        for (int64_t i = c * C; i < std::min<int64_t>(n, (c + 1) * C); ++i)
+            w = std::max<int64_t>(w, len(p.perm[i]));
+        p.width[c] = static_cast<int32_t>(w);
+        p.max_width = std::max<int32_t>(p.max_width, static_cast<int32_t>(w));
+        p.off[c + 1] = p.off[c] + w * C;
+    }
+    p.slots = p.off[p.n_chunks];
+}
+
+struct MatrixLayout {
+    size_t o_off, o_width, o_col, o_val, o_perm, o_iperm, total;
+};
+
+static MatrixLayout matrix_layout(const SellPlan &p, int prec) {
+    MatrixLayout L;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        size_t here = at;
+        at = round_up(at + bytes, 256);
+        return here;
+    };
+    L.o_off = take(sizeof(int64_t) * (p.n_chunks + 1));
+    L.o_width = take(sizeof(int32_t) * p.n_chunks);
+    L.o_col = take(sizeof(int32_t) * std::max<int64_t>(p.slots, 1));
+    L.o_val = take(vec_elem_bytes(prec) * std::max<int64_t>(p.slots, 1));
+    L.o_perm = take(sizeof(int32_t) * p.n);
+    L.o_iperm = take(sizeof(int32_t) * p.n);
+    L.total = at;
+    return L;
+}
+
+}  // namespace chebfd
+
+using namespace chebfd;
+
+extern "C" {
+
+int chebfd_version(void) { return 100; }
+
+const char *chebfd_last_error(void) { return g_error.c_str(); }
+
+int chebfd_device_info(int32_t *num_cus, char *name, int32_t name_len) {
+    DeviceProps d;
+    int rc = device_props(&d);
+    if (rc) return rc;
+    if (num_cus) *num_cus = d.num_cus;
+    if (name && name_len > 0) snprintf(name, name_len, "%s", d.name);
+    return CHEBFD_OK;
+}
+
+int chebfd_matrix_query(int64_t n, const int64_t *h_rowptr, int32_t C, int32_t sigma,
+                        int32_t prec, size_t *bytes) {
+    clear_error();
+    int rc = check_matrix_args(n, h_rowptr, C, sigma, prec);
+    if (rc) return rc;
+    CHEBFD_REQUIRE(bytes != nullptr, "bytes is NULL");
+    SellPlan p;
+    make_plan(n, h_rowptr, C, sigma, p);
+    *bytes = matrix_layout(p, prec).total;
+    return CHEBFD_OK;
+}
+
+int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col,
+                        const double *h_val, int32_t C, int32_t sigma, int32_t prec, void *d_buf,
+                        size_t bytes, void *stream, chebfd_matrix *out) {
+    clear_error();
+    int rc = check_matrix_args(n, h_rowptr, C, sigma, prec);
+    if (rc) return rc;
+    const int64_t nnz = h_rowptr[n];
+    CHEBFD_REQUIRE(nnz == 0 || (h_col && h_val), "h_col / h_val is NULL");
+    CHEBFD_REQUIRE(d_buf != nullptr && aligned(d_buf, 256), "d_buf must be non-NULL and 256-byte aligned");
+    CHEBFD_REQUIRE(out != nullptr, "out is NULL");
+    for (int64_t k = 0; k < nnz; ++k)
+        CHEBFD_REQUIRE(h_col[k] >= 0 && h_col[k] < n, "column index %d at entry %lld out of range",
+                       h_col[k], (long long)k);
+    SellPlan p;
+    make_plan(n, h_rowptr, C, sigma, p);
+    const MatrixLayout L = matrix_layout(p, prec);
+    if (bytes < L.total)
+        CHEBFD_FAIL(CHEBFD_EWORKSPACE, "matrix buffer has %zu bytes, needs %zu", bytes, L.total);
+
+    std::vector<int32_t> iperm(n);
+    for (int64_t i = 0; i < n; ++i) iperm[p.perm[i]] = static_cast<int32_t>(i);
+    std::vector<int32_t> col(std::max<int64_t>(p.slots, 1), 0);
+    std::vector<double> vd;
+    std::vector<float> vf;
+    if (prec == CHEBFD_PREC_FP64)
+        vd.assign(2 * std::max<int64_t>(p.slots, 1), 0.0);
+    else
+        vf.assign(2 * std::max<int64_t>(p.slots, 1), 0.0f);
+    for (int64_t c = 0; c < p.n_chunks; ++c) {
+        const int w = p.width[c];
+        for (int r = 0; r < C; ++r) {
+            const int64_t i = c * C + r;
+            const int64_t base = p.off[c] + r;
+            if (i >= n) {
+                for (int k = 0; k < w; ++k) col[base + (int64_t)k * C] = 0;
+                continue;
+            }
+            const int32_t old = p.perm[i];
+            const int64_t b = h_rowptr[old], len = h_rowptr[old + 1] - b;
+            for (int k = 0; k < w; ++k) {
+                const int64_t s = base + (int64_t)k * C;
+                if (k < len) {
+                    col[s] = iperm[h_col[b + k]];
+                    if (prec == CHEBFD_PREC_FP64) {
+                        vd[2 * s] = h_val[2 * (b + k)];
+                        vd[2 * s + 1] = h_val[2 * (b + k) + 1];
+                    } else {
+                        vf[2 * s] = static_cast<float>(h_val[2 * (b + k)]);
+                        vf[2 * s + 1] = static_cast<float>(h_val[2 * (b + k) + 1]);
+                    }
+                } else {
+                    col[s] = static_cast<int32_t>(i);  // padding: own row, value 0
+                }
+            }
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(d_buf);
+    CHEBFD_HIP(hipMemcpyAsync(base + L.o_off, p.off.data(), sizeof(int64_t) * (p.n_chunks + 1),
+                              hipMemcpyHostToDevice, s));
+    CHEBFD_HIP(hipMemcpyAsync(base + L.o_width, p.width.data(), sizeof(int32_t) * p.n_chunks,
+                              hipMemcpyHostToDevice, s));
+    CHEBFD_HIP(hipMemcpyAsync(base + L.o_col, col.data(), sizeof(int32_t) * col.size(),
+                              hipMemcpyHostToDevice, s));
+    if (prec == CHEBFD_PREC_FP64)
+        CHEBFD_HIP(hipMemcpyAsync(base + L.o_val, vd.data(), sizeof(double) * vd.size(),
+                                  hipMemcpyHostToDevice, s));
+    else
+        CHEBFD_HIP(hipMemcpyAsync(base + L.o_val, vf.data(), sizeof(float) * vf.size(),
+                                  hipMemcpyHostToDevice, s));
+    CHEBFD_HIP(hipMemcpyAsync(base + L.o_perm, p.perm.data(), sizeof(int32_t) * n,
+                              hipMemcpyHostToDevice, s));
+    CHEBFD_HIP(hipMemcpyAsync(base + L.o_iperm, iperm.data(), sizeof(int32_t) * n,
+                              hipMemcpyHostToDevice, s));
+    CHEBFD_HIP(hipStreamSynchronize(s));
+
+    chebfd_matrix m;
+    std::memset(&m, 0, sizeof(m));
+    m.n = n;
+    m.nnz = nnz;
+    m.n_chunks = p.n_chunks;
+    m.slots = p.slots;
+    m.C = C;
+    m.sigma = sigma;
+    m.prec = prec;
+    m.max_width = p.max_width;
+    m.identity_perm = p.identity ? 1 : 0;
+    m.chunk_off = reinterpret_cast<const int64_t *>(base + L.o_off);
+    m.chunk_width = reinterpret_cast<const int32_t *>(base + L.o_width);
+    m.col = reinterpret_cast<const int32_t *>(base + L.o_col);
+    m.val = base + L.o_val;
+    m.perm = reinterpret_cast<const int32_t *>(base + L.o_perm);
+    m.iperm = reinterpret_cast<const int32_t *>(base + L.o_iperm);
+    *out = m;
+    return CHEBFD_OK;
+}
+
+static int check_handle(const chebfd_matrix *H) {
+    CHEBFD_REQUIRE(H != nullptr, "matrix handle is NULL");
+    CHEBFD_REQUIRE(H->n >= 1 && H->chunk_off && H->chunk_width && H->col && H->val && H->perm,
+                   "matrix handle is not built");
+    CHEBFD_REQUIRE(ilog2_exact(H->C) >= 0, "matrix handle has invalid C");
+    return CHEBFD_OK;
+}
+
+static int bounds_grid(const DeviceProps &d, int64_t n) {
+    int64_t G = (n + 255) / 256;
+    G = std::min<int64_t>(G, (int64_t)d.num_cus * 4);
+    return static_cast<int>(std::max<int64_t>(G, 1));
+}
+
+int chebfd_bounds_query(const chebfd_matrix *H, size_t *work_bytes) {
+    clear_error();
+    int rc = check_handle(H);
+    if (rc) return rc;
+    CHEBFD_REQUIRE(work_bytes != nullptr, "work_bytes is NULL");
+    DeviceProps d;
+    if ((rc = device_props(&d))) return rc;
+    *work_bytes = round_up(sizeof(double) * (2 * bounds_grid(d, H->n) + 2), 256);
+    return CHEBFD_OK;
+}
+
+int chebfd_bounds(const chebfd_matrix *H, void *d_work, size_t work_bytes, void *stream,
+                  double *lam_lo, double *lam_hi) {
+    clear_error();
+    int rc = check_handle(H);
+    if (rc) return rc;
+    CHEBFD_REQUIRE(lam_lo && lam_hi, "lam_lo / lam_hi is NULL");
+    CHEBFD_REQUIRE(d_work && aligned(d_work, 256), "d_work must be non-NULL and 256-byte aligned");
+    DeviceProps d;
+    if ((rc = device_props(&d))) return rc;
+    const int G = bounds_grid(d, H->n);
+    const size_t need = round_up(sizeof(double) * (2 * G + 2), 256);
+    if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "bounds workspace %zu < %zu", work_bytes, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *part = static_cast<double *>(d_work);
+    double *res = part + 2 * G;
+    if ((rc = launch_bounds(H->chunk_off, H->chunk_width, H->col, H->val, H->prec, H->n, H->C,
+                            ilog2_exact(H->C), part, G, s)))
+        return rc;
+    if ((rc = launch_bounds_final(part, G, res, s))) return rc;
+    double h[2];
+    CHEBFD_HIP(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, s));
+    CHEBFD_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
+        CHEBFD_FAIL(CHEBFD_ENUMERIC, "non-finite Gershgorin bounds");
+    *lam_lo = h[0];
+    *lam_hi = h[1];
+    return CHEBFD_OK;
+}
+
+int chebfd_coefficients(double lam_lo, double lam_hi, double lam_L, double lam_R, int32_t n_p,
+                        double *alpha, double *beta, double *h_gamma) {
+    clear_error();
+    CHEBFD_REQUIRE(alpha && beta && h_gamma, "output pointer is NULL");
+    CHEBFD_REQUIRE(n_p >= 0, "n_p = %d < 0", n_p);
+    CHEBFD_REQUIRE(std::isfinite(lam_lo) && std::isfinite(lam_hi) && lam_hi > lam_lo,
+                   "spectral bounds [%g, %g] invalid", lam_lo, lam_hi);
+    const double al = 2.0 / (lam_hi - lam_lo);
+    const double be = -(lam_hi + lam_lo) / (lam_hi - lam_lo);
+    const double a = al * lam_L + be, b = al * lam_R + be;
+    if (!(a > -1.0 && a < b && b < 1.0))
+        CHEBFD_FAIL(CHEBFD_EINTERVAL, "scaled interval [%g, %g] not strictly inside (-1, 1)", a, b);
+    // window: Chebyshev series of the indicator of [a, b] in theta = arccos x
+    const double ta = std::acos(a), tb = std::acos(b);
+    // Jackson damping with M = n_p + 1 terms, q = pi / (M + 1)
+    const double M = n_p + 1.0;
+    const double q = M_PI / (M + 1.0);
+    const double cotq = std::cos(q) / std::sin(q);
+    for (int p = 0; p <= n_p; ++p) {
+        const double c = p == 0 ? (ta - tb) / M_PI
+                                : 2.0 * (std::sin(p * ta) - std::sin(p * tb)) / (p * M_PI);
+        const double g = ((M - p + 1.0) * std::cos(p * q) + std::sin(p * q) * cotq) / (M + 1.0);
+        h_gamma[p] = g * c;
+    }
+    *alpha = al;
+    *beta = be;
+    return CHEBFD_OK;
+}
+
+static int check_prec_nb(int32_t prec, int32_t n_b) {
+    CHEBFD_REQUIRE(prec == CHEBFD_PREC_FP64 || prec == CHEBFD_PREC_MIXED, "prec = %d invalid", prec);
+    CHEBFD_REQUIRE(n_b >= 1 && n_b <= 128 && ilog2_exact(n_b) >= 0,
+                   "n_b = %d must be a power of two in [1, 128]", n_b);
+    return CHEBFD_OK;
+}
+
+int chebfd_pack(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec,
+                const void *d_colmajor, void *d_blocked, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(prec, n_b))) return rc;
+    CHEBFD_REQUIRE(m >= 1 && m % n_b == 0, "m = %d must be a positive multiple of n_b = %d", m, n_b);
+    CHEBFD_REQUIRE(d_colmajor && d_blocked, "NULL buffer");
+    CHEBFD_REQUIRE(aligned(d_colmajor, 16) && aligned(d_blocked, 16), "buffers must be 16-byte aligned");
+    CHEBFD_REQUIRE(!overlap(d_colmajor, 16 * H->n * m, d_blocked, vec_elem_bytes(prec) * H->n * m),
+                   "source and destination overlap");
+    return launch_pack(H->identity_perm ? nullptr : H->perm, H->n, m, n_b, prec, d_colmajor,
+                       d_blocked, false, static_cast<hipStream_t>(stream));
+}
+
+int chebfd_unpack(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec,
+                  const void *d_blocked, void *d_colmajor, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(prec, n_b))) return rc;
+    CHEBFD_REQUIRE(m >= 1 && m % n_b == 0, "m = %d must be a positive multiple of n_b = %d", m, n_b);
+    CHEBFD_REQUIRE(d_colmajor && d_blocked, "NULL buffer");
+    CHEBFD_REQUIRE(aligned(d_colmajor, 16) && aligned(d_blocked, 16), "buffers must be 16-byte aligned");
+    CHEBFD_REQUIRE(!overlap(d_colmajor, 16 * H->n * m, d_blocked, vec_elem_bytes(prec) * H->n * m),
+                   "source and destination overlap");
+    return launch_pack(H->identity_perm ? nullptr : H->perm, H->n, m, n_b, prec, d_blocked,
+                       d_colmajor, true, static_cast<hipStream_t>(stream));
+}
+
+// workspace of the filter: two partial buffers [3*n_b][G] (double buffered)
+static size_t filter_work_bytes(int nb, int G) {
+    return 2 * round_up(sizeof(double) * 3 * nb * (size_t)G, 256);
+}
+
+static int filter_geometry(const chebfd_matrix *H, int prec, int nb, int64_t *npass, int *G) {
+    DeviceProps d;
+    int rc = device_props(&d);
+    if (rc) return rc;
+    const int rows = 256 / nb;
+    *npass = (H->n + rows - 1) / rows;
+    *G = step_grid(prec, nb, *npass, d.num_cus);
+    return CHEBFD_OK;
+}
+
+int chebfd_filter_query(const chebfd_matrix *H, int32_t n_b, size_t *work_bytes) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(H->prec, n_b))) return rc;
+    CHEBFD_REQUIRE(work_bytes != nullptr, "work_bytes is NULL");
+    int64_t npass;
+    int G;
+    if ((rc = filter_geometry(H, H->prec, n_b, &npass, &G))) return rc;
+    *work_bytes = filter_work_bytes(n_b, G);
+    return CHEBFD_OK;
+}
+
+static StepArgs base_args(const chebfd_matrix *H, double alpha, double beta, int64_t npass) {
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = H->n;
+    a.npass = npass;
+    a.chunk_off = H->chunk_off;
+    a.chunk_width = H->chunk_width;
+    a.col = H->col;
+    a.val = H->val;
+    a.C = H->C;
+    a.log2C = ilog2_exact(H->C);
+    a.alpha = alpha;
+    a.beta = beta;
+    return a;
+}
+
+int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
+                  int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
+                  void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,
+                  void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(prec, n_b))) return rc;
+    CHEBFD_REQUIRE(prec == H->prec, "prec %d differs from the matrix's %d", prec, H->prec);
+    CHEBFD_REQUIRE(n_p >= 0 && h_gamma != nullptr, "n_p = %d / gamma invalid", n_p);
+    CHEBFD_REQUIRE(n_s >= 1 && n_s % n_b == 0, "n_s = %d must be a positive multiple of n_b = %d", n_s, n_b);
+    CHEBFD_REQUIRE(std::isfinite(alpha) && std::isfinite(beta), "alpha/beta not finite");
+    for (int p = 0; p <= n_p; ++p)
+        CHEBFD_REQUIRE(std::isfinite(h_gamma[p]), "gamma[%d] not finite", p);
+    CHEBFD_REQUIRE((d_eta == nullptr) == (d_nu == nullptr), "d_eta and d_nu must both be set or both NULL");
+    CHEBFD_REQUIRE(d_xy && d_u && d_w && d_work, "NULL device buffer");
+    for (const void *ptr : {(const void *)d_xy, (const void *)d_u, (const void *)d_w,
+                            (const void *)d_work, (const void *)d_eta, (const void *)d_nu})
+        CHEBFD_REQUIRE(ptr == nullptr || aligned(ptr, 256), "device buffers must be 256-byte aligned");
+    const size_t eb = vec_elem_bytes(prec);
+    const size_t blk = eb * (size_t)H->n * n_b;
+    const size_t xy_bytes = blk * (n_s / n_b);
+    int64_t npass;
+    int G;
+    if ((rc = filter_geometry(H, prec, n_b, &npass, &G))) return rc;
+    const size_t need = filter_work_bytes(n_b, G);
+    if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "filter workspace %zu < %zu", work_bytes, need);
+    CHEBFD_REQUIRE(!overlap(d_xy, xy_bytes, d_u, blk) && !overlap(d_xy, xy_bytes, d_w, blk) &&
+                       !overlap(d_u, blk, d_w, blk) && !overlap(d_work, need, d_xy, xy_bytes) &&
+                       !overlap(d_work, need, d_u, blk) && !overlap(d_work, need, d_w, blk),
+                   "filter buffers overlap");
+    if (d_eta) {
+        const size_t mb = sizeof(double) * (size_t)(n_p + 1) * n_s;
+        CHEBFD_REQUIRE(!overlap(d_eta, 2 * mb, d_nu, mb), "d_eta and d_nu overlap");
+    }
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *part[2];
+    part[0] = static_cast<double *>(d_work);
+    part[1] = reinterpret_cast<double *>(static_cast<char *>(d_work) + need / 2);
+    const int nblocks = n_s / n_b;
+    const int64_t count = H->n * (int64_t)n_b;
+
+    // pending reduction: the partials of the last launch and where they go
+    const double *pend_part = nullptr;
+    double *pend_eta = nullptr, *pend_nu = nullptr;
+    int flip = 0;
+    auto next_args = [&](StepArgs a, int p, int b) {
+        a.part_out = part[flip];
+        a.part_in = pend_part;
+        a.red_eta = pend_eta;
+        a.red_nu = pend_nu;
+        a.G_prev = G;
+        pend_part = part[flip];
+        if (d_eta) {
+            pend_eta = d_eta + 2 * ((int64_t)p * n_s + (int64_t)b * n_b);
+            pend_nu = d_nu + ((int64_t)p * n_s + (int64_t)b * n_b);
+        } else {
+            pend_eta = nullptr;
+            pend_nu = nullptr;
+        }
+        if (!d_eta) a.part_in = nullptr;
+        flip ^= 1;
+        return a;
+    };
+
+    for (int b = 0; b < nblocks; ++b) {
+        char *X = static_cast<char *>(d_xy) + blk * b;
+        void *A = d_u, *B = d_w;
+        if (n_p == 0) {
+            if ((rc = launch_axpby_blocked(prec, count, h_gamma[0], X, 0.0, nullptr, s))) return rc;
+            continue;
+        }
+        StepArgs a = base_args(H, alpha, beta, npass);
+        // U <- (aH + bI) X                                         (Alg. 1 line 4)
+        a.P = X;
+        a.N = A;
+        if ((rc = launch_step(prec, n_b, kModeFirst, next_args(a, 1, b), G, s))) return rc;
+        if (n_p == 1) {
+            if ((rc = launch_axpby_blocked(prec, count, h_gamma[0], X, h_gamma[1], A, s))) return rc;
+            continue;
+        }
+        // W <- 2(aH + bI) U - X;  X <- g0c0 X + g1c1 U + g2c2 W         (lines 5-6)
+        a = base_args(H, alpha, beta, npass);
+        a.P = A;
+        a.O = X;
+        a.N = B;
+        a.Y = X;
+        a.g0 = h_gamma[0];
+        a.g1 = h_gamma[1];
+        a.g2 = h_gamma[2];
+        if ((rc = launch_step(prec, n_b, kModeSecond, next_args(a, 2, b), G, s))) return rc;
+        // p = 3..n_p: swap(W, U); chebfd_op(H, U, W, X)                  (lines 7-13)
+        void *Ub = B, *Wb = A;  // after the swap U holds T_2, W holds T_1
+        for (int p = 3; p <= n_p; ++p) {
+            a = base_args(H, alpha, beta, npass);
+            a.P = Ub;
+            a.O = Wb;
+            a.Y = X;
+            a.g2 = h_gamma[p];
+            if ((rc = launch_step(prec, n_b, kModeStep, next_args(a, p, b), G, s))) return rc;
+            std::swap(Ub, Wb);
+        }
+    }
+    if (d_eta && pend_part) {
+        StepArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.part_in = pend_part;
+        a.red_eta = pend_eta;
+        a.red_nu = pend_nu;
+        a.G_prev = G;
+        if ((rc = launch_reduce(n_b, a, s))) return rc;
+    }
+    return CHEBFD_OK;
+}
+
+int chebfd_op(const chebfd_matrix *H, double alpha, double beta, double gamma, int32_t n_b,
+              int32_t prec, const void *d_u, void *d_w, void *d_y, void *d_work, size_t work_bytes,
+              void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(prec, n_b))) return rc;
+    CHEBFD_REQUIRE(prec == H->prec, "prec %d differs from the matrix's %d", prec, H->prec);
+    CHEBFD_REQUIRE(d_u && d_w && d_y && d_work, "NULL device buffer");
+    const size_t blk = vec_elem_bytes(prec) * (size_t)H->n * n_b;
+    int64_t npass;
+    int G;
+    if ((rc = filter_geometry(H, prec, n_b, &npass, &G))) return rc;
+    const size_t need = filter_work_bytes(n_b, G);
+    if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "workspace %zu < %zu", work_bytes, need);
+    CHEBFD_REQUIRE(!overlap(d_u, blk, d_w, blk) && !overlap(d_u, blk, d_y, blk) &&
+                       !overlap(d_w, blk, d_y, blk) && !overlap(d_work, need, d_u, blk) &&
+                       !overlap(d_work, need, d_w, blk) && !overlap(d_work, need, d_y, blk),
+                   "buffers overlap");
+    StepArgs a = base_args(H, alpha, beta, npass);
+    a.P = d_u;
+    a.O = d_w;
+    a.Y = d_y;
+    a.g2 = gamma;
+    a.part_out = static_cast<double *>(d_work);
+    return launch_step(prec, n_b, kModeStep, a, G, static_cast<hipStream_t>(stream));
+}
+
+int chebfd_probe_stream(int32_t kind, int64_t count, const double *d_b, const double *d_c, double s,
+                        double *d_a, void *stream) {
+    clear_error();
+    CHEBFD_REQUIRE(kind == 0 || kind == 1, "kind = %d invalid", kind);
+    CHEBFD_REQUIRE(count >= 2 && count % 2 == 0, "count must be even and >= 2");
+    CHEBFD_REQUIRE(d_a && d_b && (kind == 0 || d_c), "NULL buffer");
+    CHEBFD_REQUIRE(aligned(d_a, 16) && aligned(d_b, 16) && (kind == 0 || aligned(d_c, 16)),
+                   "buffers must be 16-byte aligned");
+    DeviceProps d;
+    int rc = device_props(&d);
+    if (rc) return rc;
+    return launch_stream_probe(kind, count, d_b, d_c, s, d_a, d.num_cus,
+                               static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+// Support kernels: layout conversion between the caller's column-major c128
+// block and the filter's blocked row-major layout, a blocked axpby, the
+// Gershgorin bound reduction and the HBM stream probe.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace chebfd {
+
+constexpr int kT = 256;
+
+// Blocked element (b, i, j) <-> column-major element (row perm[i], column b*nb + j).
+// One thread per blocked element: writes (pack) or reads (unpack) of the blocked
+// side are contiguous; the column-major side is read/written with stride n.
+template <typename T, bool UNPACK>
+__global__ __launch_bounds__(kT) void pack_kernel(const int32_t *__restrict__ perm, int64_t n,
+                                                  int m, int nb, const void *src, void *dst) {
+    const int64_t total = n * m;
+    for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * kT) {
+        const int64_t b = t / (n * nb);
+        const int64_t rem = t - b * n * nb;
+        const int64_t i = rem / nb;
+        const int j = static_cast<int>(rem - i * nb);
+        const int64_t row = perm ? perm[i] : i;
+        const int64_t cm = (b * nb + j) * n + row;  // column-major index
+        if constexpr (!UNPACK) {
+            const double2 v = static_cast<const double2 *>(src)[cm];
+            if constexpr (sizeof(T) == 8) {
+                static_cast<double2 *>(dst)[t] = v;
+            } else {
+                float2 f;
+                f.x = static_cast<float>(v.x);
+                f.y = static_cast<float>(v.y);
+                static_cast<float2 *>(dst)[t] = f;
+            }
+        } else {
+            double2 v;
+            if constexpr (sizeof(T) == 8) {
+                v = static_cast<const double2 *>(src)[t];
+            } else {
+                const float2 f = static_cast<const float2 *>(src)[t];
+                v.x = f.x;
+                v.y = f.y;
+            }
+            static_cast<double2 *>(dst)[cm] = v;
+        }
+    }
+}
+
+static int grid_for(int64_t work, int cap = 65536) {
+    int64_t g = (work + kT - 1) / kT;
+    if (g > cap) g = cap;
+    return static_cast<int>(g < 1 ? 1 : g);
+}
+
+int launch_pack(const int32_t *perm, int64_t n, int m, int nb, int prec, const void *src,
+                void *dst, bool unpack, hipStream_t s) {
+    const int G = grid_for(n * m);
+    if (prec == CHEBFD_PREC_FP64) {
+        if (unpack)
+            hipLaunchKernelGGL((pack_kernel<double, true>), dim3(G), dim3(kT), 0, s, perm, n, m, nb, src, dst);
+        else
+            hipLaunchKernelGGL((pack_kernel<double, false>), dim3(G), dim3(kT), 0, s, perm, n, m, nb, src, dst);
+    } else {
+        if (unpack)
+            hipLaunchKernelGGL((pack_kernel<float, true>), dim3(G), dim3(kT), 0, s, perm, n, m, nb, src, dst);
+        else
+            hipLaunchKernelGGL((pack_kernel<float, false>), dim3(G), dim3(kT), 0, s, perm, n, m, nb, src, dst);
+    }
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+// y <- a*y + b*x elementwise over `count` complex entries (degree 0 and 1 filters)
+template <typename T>
+__global__ __launch_bounds__(kT) void axpby_kernel(int64_t count, double a, T *y, double b,
+                                                   const T *x) {
+    for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < 2 * count;
+         t += (int64_t)gridDim.x * kT) {
+        const double xv = x ? static_cast<double>(x[t]) : 0.0;
+        y[t] = static_cast<T>(a * static_cast<double>(y[t]) + b * xv);
+    }
+}
+
+int launch_axpby_blocked(int prec, int64_t count, double a, void *y, double b, const void *x,
+                         hipStream_t s) {
+    const int G = grid_for(2 * count);
+    if (prec == CHEBFD_PREC_FP64)
+        hipLaunchKernelGGL((axpby_kernel<double>), dim3(G), dim3(kT), 0, s, count, a,
+                           static_cast<double *>(y), b, static_cast<const double *>(x));
+    else
+        hipLaunchKernelGGL((axpby_kernel<float>), dim3(G), dim3(kT), 0, s, count, a,
+                           static_cast<float *>(y), b, static_cast<const float *>(x));
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+// Gershgorin: per row c = Re(diagonal), r = sum of |off-diagonal|; per
+// workgroup min(c - r) and max(c + r) -> part[2*w], part[2*w + 1].
+template <typename T>
+__global__ __launch_bounds__(kT) void bounds_kernel(const int64_t *__restrict__ chunk_off,
+                                                    const int32_t *__restrict__ chunk_width,
+                                                    const int32_t *__restrict__ col,
+                                                    const T *__restrict__ val, int64_t n, int C,
+                                                    int log2C, double *part) {
+    __shared__ double slo[kT], shi[kT];
+    double lo = 1.0 / 0.0, hi = -1.0 / 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+        const int64_t c = i >> log2C;
+        const int64_t off = chunk_off[c] + (i & (C - 1));
+        const int wdt = chunk_width[c];
+        double d = 0.0, r = 0.0;
+        for (int k = 0; k < wdt; ++k) {
+            const int64_t sidx = off + (int64_t)k * C;
+            const double re = static_cast<double>(val[2 * sidx]);
+            const double im = static_cast<double>(val[2 * sidx + 1]);
+            if (col[sidx] == i)
+                d += re;
+            else
+                r += sqrt(re * re + im * im);
+        }
+        lo = fmin(lo, d - r);
+        hi = fmax(hi, d + r);
+    }
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int h = kT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + h]);
+            shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = slo[0];
+        part[2 * blockIdx.x + 1] = shi[0];
+    }
+}
+
+__global__ __launch_bounds__(kT) void bounds_final_kernel(const double *part, int G, double *out) {
+    __shared__ double slo[kT], shi[kT];
+    double lo = 1.0 / 0.0, hi = -1.0 / 0.0;
+    for (int g = threadIdx.x; g < G; g += kT) {
+        lo = fmin(lo, part[2 * g]);
+        hi = fmax(hi, part[2 * g + 1]);
+    }
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int h = kT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + h]);
+            shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = slo[0];
+        out[1] = shi[0];
+    }
+}
+
+int launch_bounds(const int64_t *chunk_off, const int32_t *chunk_width, const int32_t *col,
+                  const void *val, int prec, int64_t n, int C, int log2C, double *part, int G,
+                  hipStream_t s) {
+    if (prec == CHEBFD_PREC_FP64)
+        hipLaunchKernelGGL((bounds_kernel<double>), dim3(G), dim3(kT), 0, s, chunk_off, chunk_width,
+                           col, static_cast<const double *>(val), n, C, log2C, part);
+    else
+        hipLaunchKernelGGL((bounds_kernel<float>), dim3(G), dim3(kT), 0, s, chunk_off, chunk_width,
+                           col, static_cast<const float *>(val), n, C, log2C, part);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int launch_bounds_final(const double *part, int G, double *out2, hipStream_t s) {
+    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(kT), 0, s, part, G, out2);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+// STREAM-style probe over doubles, 16-byte vector accesses, grid-stride.
+__global__ __launch_bounds__(kT) void copy_kernel(int64_t n2, const double2 *__restrict__ b,
+                                                  double2 *__restrict__ a) {
+    for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < n2; t += (int64_t)gridDim.x * kT)
+        a[t] = b[t];
+}
+
+__global__ __launch_bounds__(kT) void triad_kernel(int64_t n2, const double2 *__restrict__ b,
+                                                   const double2 *__restrict__ c, double s,
+                                                   double2 *__restrict__ a) {
+    for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < n2;
+         t += (int64_t)gridDim.x * kT) {
+        const double2 x = b[t], y = c[t];
+        double2 r;
+        r.x = fma(s, y.x, x.x);
+        r.y = fma(s, y.y, x.y);
+        a[t] = r;
+    }
+}
+
+int launch_stream_probe(int kind, int64_t count, const double *b, const double *c, double sc,
+                        double *a, int num_cus, hipStream_t s) {
+    const int64_t n2 = count / 2;
+    int64_t G = (n2 + kT - 1) / kT;
+    const int64_t cap = static_cast<int64_t>(num_cus) * 16;
+    if (G > cap) G = cap;
+    if (G < 1) G = 1;
+    if (kind == 0)
+        hipLaunchKernelGGL(copy_kernel, dim3(G), dim3(kT), 0, s, n2,
+                           reinterpret_cast<const double2 *>(b), reinterpret_cast<double2 *>(a));
+    else
+        hipLaunchKernelGGL(triad_kernel, dim3(G), dim3(kT), 0, s, n2,
+                           reinterpret_cast<const double2 *>(b), reinterpret_cast<const double2 *>(c),
+                           sc, reinterpret_cast<double2 *>(a));
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+}  // namespace chebfd
