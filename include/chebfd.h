@@ -69,7 +69,7 @@ typedef struct chebfd_matrix {
     int32_t prec;               /* CHEBFD_PREC_* of the stored values */
     int32_t max_width;          /* longest row */
     int32_t identity_perm;      /* 1 if the permutation is the identity */
-    int32_t reserved;
+    int32_t uniform_width;      /* slots per row of every chunk if all chunks are equally wide, else 0 */
     const int64_t *chunk_off;   /* [n_chunks + 1] first slot of each chunk */
     const int32_t *chunk_width; /* [n_chunks] slots per row in the chunk */
     const int32_t *col;         /* [slots] permuted column index */

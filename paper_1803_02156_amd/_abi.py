@@ -19,7 +19,7 @@ class ChebfdMatrix(ctypes.Structure):
     _fields_ = [
         ("n", i64), ("nnz", i64), ("n_chunks", i64), ("slots", i64),
         ("C", i32), ("sigma", i32), ("prec", i32), ("max_width", i32),
-        ("identity_perm", i32), ("reserved", i32),
+        ("identity_perm", i32), ("uniform_width", i32),
         ("chunk_off", P), ("chunk_width", P), ("col", P), ("val", P),
         ("perm", P), ("iperm", P),
     ]

@@ -113,11 +113,14 @@ static void make_plan(int64_t n, const int64_t *rowptr, int32_t C, int32_t sigma
     p.slots = p.off[p.n_chunks];
 }
 
+// stored slots plus the zero padding the unrolled row kernel may read past the end
+static int64_t padded_slots(const SellPlan &p, int C) { return p.slots + (int64_t)kRowMaxUnrolled * C; }
+
 struct MatrixLayout {
     size_t o_off, o_width, o_col, o_val, o_perm, o_iperm, total;
 };
 
-static MatrixLayout matrix_layout(const SellPlan &p, int prec) {
+static MatrixLayout matrix_layout(const SellPlan &p, int prec, int C) {
     MatrixLayout L;
     size_t at = 0;
     auto take = [&](size_t bytes) {
@@ -127,8 +130,8 @@ static MatrixLayout matrix_layout(const SellPlan &p, int prec) {
     };
     L.o_off = take(sizeof(int64_t) * (p.n_chunks + 1));
     L.o_width = take(sizeof(int32_t) * p.n_chunks);
-    L.o_col = take(sizeof(int32_t) * std::max<int64_t>(p.slots, 1));
-    L.o_val = take(vec_elem_bytes(prec) * std::max<int64_t>(p.slots, 1));
+    L.o_col = take(sizeof(int32_t) * padded_slots(p, C));
+    L.o_val = take(vec_elem_bytes(prec) * padded_slots(p, C));
     L.o_perm = take(sizeof(int32_t) * p.n);
     L.o_iperm = take(sizeof(int32_t) * p.n);
     L.total = at;
@@ -162,7 +165,7 @@ int chebfd_matrix_query(int64_t n, const int64_t *h_rowptr, int32_t C, int32_t s
     CHEBFD_REQUIRE(bytes != nullptr, "bytes is NULL");
     SellPlan p;
     make_plan(n, h_rowptr, C, sigma, p);
-    *bytes = matrix_layout(p, prec).total;
+    *bytes = matrix_layout(p, prec, C).total;
     return CHEBFD_OK;
 }
 
@@ -181,19 +184,20 @@ int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col
                        h_col[k], (long long)k);
     SellPlan p;
     make_plan(n, h_rowptr, C, sigma, p);
-    const MatrixLayout L = matrix_layout(p, prec);
+    const MatrixLayout L = matrix_layout(p, prec, C);
     if (bytes < L.total)
         CHEBFD_FAIL(CHEBFD_EWORKSPACE, "matrix buffer has %zu bytes, needs %zu", bytes, L.total);
 
     std::vector<int32_t> iperm(n);
     for (int64_t i = 0; i < n; ++i) iperm[p.perm[i]] = static_cast<int32_t>(i);
-    std::vector<int32_t> col(std::max<int64_t>(p.slots, 1), 0);
+    const int64_t pslots = padded_slots(p, C);
+    std::vector<int32_t> col(pslots, 0);
     std::vector<double> vd;
     std::vector<float> vf;
     if (prec == CHEBFD_PREC_FP64)
-        vd.assign(2 * std::max<int64_t>(p.slots, 1), 0.0);
+        vd.assign(2 * pslots, 0.0);
     else
-        vf.assign(2 * std::max<int64_t>(p.slots, 1), 0.0f);
+        vf.assign(2 * pslots, 0.0f);
     for (int64_t c = 0; c < p.n_chunks; ++c) {
         const int w = p.width[c];
         for (int r = 0; r < C; ++r) {
@@ -253,6 +257,9 @@ int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col
     m.prec = prec;
     m.max_width = p.max_width;
     m.identity_perm = p.identity ? 1 : 0;
+    m.uniform_width = p.max_width;
+    for (int64_t c = 0; c < p.n_chunks; ++c)
+        if (p.width[c] != p.max_width) { m.uniform_width = 0; break; }
     m.chunk_off = reinterpret_cast<const int64_t *>(base + L.o_off);
     m.chunk_width = reinterpret_cast<const int32_t *>(base + L.o_width);
     m.col = reinterpret_cast<const int32_t *>(base + L.o_col);
@@ -386,14 +393,48 @@ static size_t filter_work_bytes(int nb, int G) {
     return 2 * round_up(sizeof(double) * 3 * nb * (size_t)G, 256);
 }
 
-static int filter_geometry(const chebfd_matrix *H, int prec, int nb, int64_t *npass, int *G) {
+// Launch geometry of the step kernels.  The LDS-staged kernel is used whenever
+// a tile's slots fit its LDS budget (every matrix with rows up to a few hundred
+// entries); otherwise n_b >= 32 uses the row-per-wavefront kernel and smaller
+// n_b the multi-row kernel.
+struct StepGeometry {
+    int kind;           // 0 = LDS-staged, 1 = row per wavefront, 2 = multi-row
+    int64_t npass;      // passes (kinds 1, 2)
+    int G;
+    LdsGeometry lds;
+};
+
+static int filter_geometry(const chebfd_matrix *H, int prec, int nb, StepGeometry *g) {
     DeviceProps d;
     int rc = device_props(&d);
     if (rc) return rc;
-    const int rows = 256 / nb;
-    *npass = (H->n + rows - 1) / rows;
-    *G = step_grid(prec, nb, *npass, d.num_cus);
+    if (lds_geometry(H, prec, nb, d.num_cus, &g->lds)) {
+        g->kind = 0;
+        g->npass = g->lds.ntiles;
+        g->G = g->lds.G;
+    } else if (nb >= kRowKernelMinNb) {
+        g->kind = 1;
+        const int rows = row_kernel_rows_per_pass(nb);
+        g->npass = (H->n + rows - 1) / rows;
+        int64_t G = static_cast<int64_t>(d.num_cus) * row_occupancy(prec, nb);
+        if (G > g->npass) G = g->npass;
+        if (G >= 8) G -= G % 8;
+        g->G = static_cast<int>(G < 1 ? 1 : G);
+    } else {
+        g->kind = 2;
+        const int rows = 256 / nb;
+        g->npass = (H->n + rows - 1) / rows;
+        g->G = step_grid(prec, nb, g->npass, d.num_cus);
+    }
     return CHEBFD_OK;
+}
+
+static int launch_any(const chebfd_matrix *H, int prec, int nb, int mode, StepArgs a,
+                      const StepGeometry &g, hipStream_t s) {
+    a.npass = g.npass;
+    if (g.kind == 0) return launch_lds_step(prec, nb, mode, a, g.lds, s);
+    if (g.kind == 1) return launch_row_step(prec, nb, H->max_width, mode, a, g.G, s);
+    return launch_step(prec, nb, mode, a, g.G, s);
 }
 
 int chebfd_filter_query(const chebfd_matrix *H, int32_t n_b, size_t *work_bytes) {
@@ -401,18 +442,17 @@ int chebfd_filter_query(const chebfd_matrix *H, int32_t n_b, size_t *work_bytes)
     int rc;
     if ((rc = check_handle(H)) || (rc = check_prec_nb(H->prec, n_b))) return rc;
     CHEBFD_REQUIRE(work_bytes != nullptr, "work_bytes is NULL");
-    int64_t npass;
-    int G;
-    if ((rc = filter_geometry(H, H->prec, n_b, &npass, &G))) return rc;
-    *work_bytes = filter_work_bytes(n_b, G);
+    StepGeometry g;
+    if ((rc = filter_geometry(H, H->prec, n_b, &g))) return rc;
+    *work_bytes = filter_work_bytes(n_b, g.G);
     return CHEBFD_OK;
 }
 
-static StepArgs base_args(const chebfd_matrix *H, double alpha, double beta, int64_t npass) {
+static StepArgs base_args(const chebfd_matrix *H, double alpha, double beta) {
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.n = H->n;
-    a.npass = npass;
+    a.n_chunks = H->n_chunks;
     a.chunk_off = H->chunk_off;
     a.chunk_width = H->chunk_width;
     a.col = H->col;
@@ -421,6 +461,7 @@ static StepArgs base_args(const chebfd_matrix *H, double alpha, double beta, int
     a.log2C = ilog2_exact(H->C);
     a.alpha = alpha;
     a.beta = beta;
+    a.uniform_width = H->uniform_width;
     return a;
 }
 
@@ -445,9 +486,9 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
     const size_t eb = vec_elem_bytes(prec);
     const size_t blk = eb * (size_t)H->n * n_b;
     const size_t xy_bytes = blk * (n_s / n_b);
-    int64_t npass;
-    int G;
-    if ((rc = filter_geometry(H, prec, n_b, &npass, &G))) return rc;
+    StepGeometry geo;
+    if ((rc = filter_geometry(H, prec, n_b, &geo))) return rc;
+    const int G = geo.G;
     const size_t need = filter_work_bytes(n_b, G);
     if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "filter workspace %zu < %zu", work_bytes, need);
     CHEBFD_REQUIRE(!overlap(d_xy, xy_bytes, d_u, blk) && !overlap(d_xy, xy_bytes, d_w, blk) &&
@@ -496,17 +537,17 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
             if ((rc = launch_axpby_blocked(prec, count, h_gamma[0], X, 0.0, nullptr, s))) return rc;
             continue;
         }
-        StepArgs a = base_args(H, alpha, beta, npass);
+        StepArgs a = base_args(H, alpha, beta);
         // U <- (aH + bI) X                                         (Alg. 1 line 4)
         a.P = X;
         a.N = A;
-        if ((rc = launch_step(prec, n_b, kModeFirst, next_args(a, 1, b), G, s))) return rc;
+        if ((rc = launch_any(H, prec, n_b, kModeFirst, next_args(a, 1, b), geo, s))) return rc;
         if (n_p == 1) {
             if ((rc = launch_axpby_blocked(prec, count, h_gamma[0], X, h_gamma[1], A, s))) return rc;
             continue;
         }
         // W <- 2(aH + bI) U - X;  X <- g0c0 X + g1c1 U + g2c2 W         (lines 5-6)
-        a = base_args(H, alpha, beta, npass);
+        a = base_args(H, alpha, beta);
         a.P = A;
         a.O = X;
         a.N = B;
@@ -514,16 +555,16 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
         a.g0 = h_gamma[0];
         a.g1 = h_gamma[1];
         a.g2 = h_gamma[2];
-        if ((rc = launch_step(prec, n_b, kModeSecond, next_args(a, 2, b), G, s))) return rc;
+        if ((rc = launch_any(H, prec, n_b, kModeSecond, next_args(a, 2, b), geo, s))) return rc;
         // p = 3..n_p: swap(W, U); chebfd_op(H, U, W, X)                  (lines 7-13)
         void *Ub = B, *Wb = A;  // after the swap U holds T_2, W holds T_1
         for (int p = 3; p <= n_p; ++p) {
-            a = base_args(H, alpha, beta, npass);
+            a = base_args(H, alpha, beta);
             a.P = Ub;
             a.O = Wb;
             a.Y = X;
             a.g2 = h_gamma[p];
-            if ((rc = launch_step(prec, n_b, kModeStep, next_args(a, p, b), G, s))) return rc;
+            if ((rc = launch_any(H, prec, n_b, kModeStep, next_args(a, p, b), geo, s))) return rc;
             std::swap(Ub, Wb);
         }
     }
@@ -548,22 +589,22 @@ int chebfd_op(const chebfd_matrix *H, double alpha, double beta, double gamma, i
     CHEBFD_REQUIRE(prec == H->prec, "prec %d differs from the matrix's %d", prec, H->prec);
     CHEBFD_REQUIRE(d_u && d_w && d_y && d_work, "NULL device buffer");
     const size_t blk = vec_elem_bytes(prec) * (size_t)H->n * n_b;
-    int64_t npass;
-    int G;
-    if ((rc = filter_geometry(H, prec, n_b, &npass, &G))) return rc;
+    StepGeometry geo;
+    if ((rc = filter_geometry(H, prec, n_b, &geo))) return rc;
+    const int G = geo.G;
     const size_t need = filter_work_bytes(n_b, G);
     if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "workspace %zu < %zu", work_bytes, need);
     CHEBFD_REQUIRE(!overlap(d_u, blk, d_w, blk) && !overlap(d_u, blk, d_y, blk) &&
                        !overlap(d_w, blk, d_y, blk) && !overlap(d_work, need, d_u, blk) &&
                        !overlap(d_work, need, d_w, blk) && !overlap(d_work, need, d_y, blk),
                    "buffers overlap");
-    StepArgs a = base_args(H, alpha, beta, npass);
+    StepArgs a = base_args(H, alpha, beta);
     a.P = d_u;
     a.O = d_w;
     a.Y = d_y;
     a.g2 = gamma;
     a.part_out = static_cast<double *>(d_work);
-    return launch_step(prec, n_b, kModeStep, a, G, static_cast<hipStream_t>(stream));
+    return launch_any(H, prec, n_b, kModeStep, a, geo, static_cast<hipStream_t>(stream));
 }
 
 int chebfd_probe_stream(int32_t kind, int64_t count, const double *d_b, const double *d_c, double s,

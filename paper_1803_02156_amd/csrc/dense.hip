@@ -1,0 +1,714 @@
+// Dense kernels of the orthogonalisation and Rayleigh-Ritz steps (gfx950):
+//  * tall-skinny Gram  S = A^H B  over the rows of two blocked block vectors
+//    (FP64 MFMA, split over row ranges, deterministic fixed-order reduction);
+//  * tall-skinny update  Z = A M  with a small FP64 complex matrix M (FP64 MFMA);
+//  * a cyclic Jacobi eigensolver for small Hermitian matrices (one workgroup);
+//  * column norms, scaled copies and the residual reduction.
+//
+// Block vectors use the filter's blocked layout: element (i, c) of an n x m
+// block vector with block width nb is at ((c / nb) n + i) nb + c % nb, stored
+// as c128 (prec FP64) or c64 (prec MIXED).  Small matrices are FP64 complex,
+// column-major with leading dimension ld.
+//
+// MFMA: v_mfma_f64_16x16x4_f64 computes D(16x16) += A(16x4) B(4x16); lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 (l / 16) + r][l % 16] in its r-th accumulator (r = 0..3).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace chebfd {
+
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 256;
+
+__device__ inline double2 load_c(const void *base, int prec, int64_t idx) {
+    if (prec == CHEBFD_PREC_FP64) return static_cast<const double2 *>(base)[idx];
+    const float2 f = static_cast<const float2 *>(base)[idx];
+    double2 r;
+    r.x = f.x;
+    r.y = f.y;
+    return r;
+}
+
+__device__ inline void store_c(void *base, int prec, int64_t idx, double2 v) {
+    if (prec == CHEBFD_PREC_FP64) {
+        static_cast<double2 *>(base)[idx] = v;
+    } else {
+        float2 f;
+        f.x = static_cast<float>(v.x);
+        f.y = static_cast<float>(v.y);
+        static_cast<float2 *>(base)[idx] = f;
+    }
+}
+
+__device__ inline int64_t blocked_index(int64_t n, int nb, int64_t i, int c) {
+    return ((int64_t)(c / nb) * n + i) * nb + (c % nb);
+}
+
+// ---------------------------------------------------------------------------
+// Gram: S(a, b) = sum_i conj(A(i, a)) B(i, b), 64 x 64 complex output tile per
+// workgroup (4 waves, 32 x 32 each = 2 x 2 MFMA tiles x 4 real products), rows
+// [r0, r1) of one split; partial tiles go to part[split][tile] and are summed
+// in split order by gram_reduce_kernel.
+// ---------------------------------------------------------------------------
+constexpr int kGT = 64;   // output tile edge
+constexpr int kGK = 16;   // rows per LDS stage
+
+__global__ __launch_bounds__(kT) void gram_kernel(const void *A, const void *B, int prec, int64_t n,
+                                                   int nb, int m1, int m2, int tiles_a,
+                                                   int tiles_b, int64_t rows_per_split,
+                                                   double *part) {
+    __shared__ double2 sa[kGK][kGT];
+    __shared__ double2 sb[kGK][kGT];
+    const int tile = blockIdx.x;
+    const int split = blockIdx.y;
+    const int ta = tile % tiles_a, tb = tile / tiles_a;
+    const int a0 = ta * kGT, b0 = tb * kGT;
+    const int64_t r0 = (int64_t)split * rows_per_split;
+    const int64_t r1 = r0 + rows_per_split < n ? r0 + rows_per_split : n;
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int wa = (wv & 1) * 32, wb = (wv >> 1) * 32;  // wave's 32 x 32 sub-tile
+
+    d4v acc[2][2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t rb = r0; rb < r1; rb += kGK) {
+        // stage kGK rows x 64 columns of A and of B (zero outside the matrices)
+        for (int t = threadIdx.x; t < kGK * kGT; t += kT) {
+            const int rr = t / kGT, cc = t % kGT;
+            const int64_t i = rb + rr;
+            double2 va = {0.0, 0.0}, vb = {0.0, 0.0};
+            if (i < r1) {
+                if (a0 + cc < m1) va = load_c(A, prec, blocked_index(n, nb, i, a0 + cc));
+                if (b0 + cc < m2) vb = load_c(B, prec, blocked_index(n, nb, i, b0 + cc));
+            }
+            sa[rr][cc] = va;
+            sb[rr][cc] = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k0 = 0; k0 < kGK; k0 += 4) {
+            const int kk = k0 + lane / 16;
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const double2 av = sa[kk][wa + 16 * x + lane % 16];
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    const double2 bv = sb[kk][wb + 16 * y + lane % 16];
+                    // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
+                    acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, acc[x][y][0], 0, 0, 0);
+                    acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, acc[x][y][1], 0, 0, 0);
+                    acc[x][y][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, acc[x][y][2], 0, 0, 0);
+                    acc[x][y][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, acc[x][y][3], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // write the 64 x 64 partial tile (column-major inside the tile)
+    double2 *out = reinterpret_cast<double2 *>(part) +
+                   ((int64_t)split * gridDim.x + tile) * (kGT * kGT);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ra = wa + 16 * x + 4 * (lane / 16) + r;  // row of S (column of A)
+                const int cb = wb + 16 * y + lane % 16;            // column of S
+                double2 v;
+                v.x = acc[x][y][0][r] + acc[x][y][1][r];
+                v.y = acc[x][y][2][r] - acc[x][y][3][r];
+                out[(int64_t)cb * kGT + ra] = v;
+            }
+}
+
+// S = sum over splits (in split order) of the partial tiles; S column-major, ld
+__global__ __launch_bounds__(kT) void gram_reduce_kernel(const double *part, int nsplit, int ntiles,
+                                                         int tiles_a, int m1, int m2, double *S,
+                                                         int ld) {
+    const int64_t total = (int64_t)ntiles * kGT * kGT;
+    const double2 *p = reinterpret_cast<const double2 *>(part);
+    for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
+        const int tile = static_cast<int>(t / (kGT * kGT));
+        const int e = static_cast<int>(t % (kGT * kGT));
+        const int ra = e % kGT, cb = e / kGT;
+        const int a = (tile % tiles_a) * kGT + ra, b = (tile / tiles_a) * kGT + cb;
+        if (a >= m1 || b >= m2) continue;
+        double sr = 0.0, si = 0.0;
+        for (int s = 0; s < nsplit; ++s) {
+            const double2 v = p[((int64_t)s * ntiles + tile) * (kGT * kGT) + e];
+            sr += v.x;
+            si += v.y;
+        }
+        reinterpret_cast<double2 *>(S)[(int64_t)b * ld + a] = double2{sr, si};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Update: Z(i, c) = sum_k A(i, k) M(k, c), M FP64 complex column-major (ld).
+// 64 rows x 64 columns of Z per workgroup; k staged 16 at a time.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void update_kernel(const void *A, int prec_a, int nb_a,
+                                                    const double *M, int ldm, void *Z, int prec_z,
+                                                    int nb_z, int64_t n, int m1, int m2) {
+    __shared__ double2 sa[kGT][kGK + 1];
+    __shared__ double2 sm[kGK][kGT];
+    const int64_t i0 = (int64_t)blockIdx.x * kGT;
+    const int c0 = blockIdx.y * kGT;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int wi = (wv & 1) * 32, wc = (wv >> 1) * 32;
+    const double2 *Mc = reinterpret_cast<const double2 *>(M);
+
+    d4v acc[2][2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < m1; k0 += kGK) {
+        for (int t = threadIdx.x; t < kGT * kGK; t += kT) {
+            const int rr = t / kGK, kk = t % kGK;
+            const int64_t i = i0 + rr;
+            double2 v = {0.0, 0.0};
+            if (i < n && k0 + kk < m1) v = load_c(A, prec_a, blocked_index(n, nb_a, i, k0 + kk));
+            sa[rr][kk] = v;
+        }
+        for (int t = threadIdx.x; t < kGK * kGT; t += kT) {
+            const int kk = t / kGT, cc = t % kGT;
+            double2 v = {0.0, 0.0};
+            if (k0 + kk < m1 && c0 + cc < m2) v = Mc[(int64_t)(c0 + cc) * ldm + k0 + kk];
+            sm[kk][cc] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < kGK; kb += 4) {
+            const int kk = kb + lane / 16;
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const double2 av = sa[wi + 16 * x + lane % 16][kk];
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    const double2 mv = sm[kk][wc + 16 * y + lane % 16];
+                    // a m = (ar mr - ai mi) + i (ar mi + ai mr)
+                    acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, mv.x, acc[x][y][0], 0, 0, 0);
+                    acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, mv.y, acc[x][y][1], 0, 0, 0);
+                    acc[x][y][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, mv.y, acc[x][y][2], 0, 0, 0);
+                    acc[x][y][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, mv.x, acc[x][y][3], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + wi + 16 * x + 4 * (lane / 16) + r;
+                const int c = c0 + wc + 16 * y + lane % 16;
+                if (i < n && c < m2) {
+                    double2 v;
+                    v.x = acc[x][y][0][r] - acc[x][y][1][r];
+                    v.y = acc[x][y][2][r] + acc[x][y][3][r];
+                    store_c(Z, prec_z, blocked_index(n, nb_z, i, c), v);
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Cyclic Jacobi eigensolver for a Hermitian m x m FP64 complex matrix (one
+// workgroup).  Rounds of the round-robin ordering rotate m/2 disjoint (p, q)
+// pairs: all rotation parameters of a round are formed first, then the column
+// rotations A <- A J and V <- V J, then the row rotations A <- J^H A.
+// For the pair block [[a, b], [conj(b), d]], b = |b| e^{i phi}, the rotation is
+// J = diag(1, e^{-i phi}) [[c, s], [-s, c]] with t = s / c the smaller root of
+// t^2 + 2 zeta t - 1 = 0, zeta = (d - a) / (2 |b|).
+// A is overwritten; w receives the eigenvalues ascending, V (ld) the
+// eigenvectors in the same order.  info[0] = sweeps used, info[1] = 1 if the
+// off-diagonal norm did not reach the tolerance.
+// ---------------------------------------------------------------------------
+constexpr int kJT = 1024;
+constexpr int kMaxM = 512;
+
+__device__ inline int rr_player(int m, int r, int k) {
+    // round r, seat k of the circle method over players 0..m-1 (m even):
+    // seat 0 holds player 0, the other seats rotate over 1..m-1
+    return k == 0 ? 0 : ((k - 1 + r) % (m - 1)) + 1;
+}
+
+__global__ __launch_bounds__(kJT) void jacobi_kernel(int m, double *A, int lda, double *V, int ldv,
+                                                     double *w, int max_sweeps, double tol,
+                                                     int *info, double *scratch) {
+    __shared__ double s_c[kMaxM / 2], s_sr[kMaxM / 2], s_si[kMaxM / 2];
+    __shared__ int s_p[kMaxM / 2], s_q[kMaxM / 2];
+    __shared__ double s_red[kJT];
+    __shared__ int s_done;
+    double2 *Ac = reinterpret_cast<double2 *>(A);
+    double2 *Vc = reinterpret_cast<double2 *>(V);
+    const int tid = threadIdx.x;
+    const int me = m + (m & 1);  // players (a dummy player m when m is odd)
+    const int half = me / 2;
+
+    for (int t = tid; t < m * m; t += kJT) {
+        const int r = t % m, c = t / m;
+        Vc[(int64_t)c * ldv + r] = double2{r == c ? 1.0 : 0.0, 0.0};
+    }
+    // Frobenius norm for the stopping test
+    double fr = 0.0;
+    for (int t = tid; t < m * m; t += kJT) {
+        const double2 v = Ac[(int64_t)(t / m) * lda + t % m];
+        fr += v.x * v.x + v.y * v.y;
+    }
+    s_red[tid] = fr;
+    __syncthreads();
+    for (int h = kJT / 2; h > 0; h >>= 1) {
+        if (tid < h) s_red[tid] += s_red[tid + h];
+        __syncthreads();
+    }
+    const double fro2 = s_red[0];
+    __syncthreads();
+
+    int sweep = 0;
+    bool converged = false;
+    for (sweep = 0; sweep < max_sweeps && !converged && m > 1; ++sweep) {
+        for (int r = 0; r < me - 1; ++r) {
+            // rotation parameters of this round
+            for (int k = tid; k < half; k += kJT) {
+                int p = rr_player(me, r, k), q = rr_player(me, r, me - 1 - k);
+                if (p > q) { const int tmp = p; p = q; q = tmp; }
+                double c = 1.0, sr = 0.0, si = 0.0;
+                if (q < m) {
+                    const double a = Ac[(int64_t)p * lda + p].x;
+                    const double d = Ac[(int64_t)q * lda + q].x;
+                    const double2 b = Ac[(int64_t)q * lda + p];  // A[p][q]
+                    const double ab = sqrt(b.x * b.x + b.y * b.y);
+                    if (ab > 0.0) {
+                        const double zeta = (d - a) / (2.0 * ab);
+                        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        const double s = t * c;
+                        // e^{-i phi} = conj(b) / |b|
+                        sr = s * b.x / ab;
+                        si = -s * b.y / ab;
+                    }
+                }
+                s_p[k] = p;
+                s_q[k] = q;
+                s_c[k] = c;
+                s_sr[k] = sr;  // s e^{-i phi}
+                s_si[k] = si;
+            }
+            __syncthreads();
+            // columns: A(:,p) <- c A(:,p) - s e^{-i phi} A(:,q); A(:,q) <- s A(:,p) + c e^{-i phi} A(:,q)
+            // (same for V), with s e^{-i phi} = (sr, si) and e^{-i phi} = (sr, si) / s
+            for (int t = tid; t < half * m; t += kJT) {
+                const int k = t / m, row = t % m;
+                const int p = s_p[k], q = s_q[k];
+                if (q >= m) continue;
+                const double c = s_c[k], sr = s_sr[k], si = s_si[k];
+                const double s = sqrt(sr * sr + si * si);
+                const double er = s > 0.0 ? sr / s : 1.0, ei = s > 0.0 ? si / s : 0.0;
+                for (int which = 0; which < 2; ++which) {
+                    double2 *M = which ? Vc : Ac;
+                    const int ld = which ? ldv : lda;
+                    const double2 x = M[(int64_t)p * ld + row], y = M[(int64_t)q * ld + row];
+                    double2 np, nq;
+                    // np = c x - (sr + i si) y
+                    np.x = c * x.x - (sr * y.x - si * y.y);
+                    np.y = c * x.y - (sr * y.y + si * y.x);
+                    // nq = s x + c (er + i ei) y
+                    nq.x = s * x.x + c * (er * y.x - ei * y.y);
+                    nq.y = s * x.y + c * (er * y.y + ei * y.x);
+                    M[(int64_t)p * ld + row] = np;
+                    M[(int64_t)q * ld + row] = nq;
+                }
+            }
+            __syncthreads();
+            // rows: A(p,:) <- c A(p,:) - s e^{i phi} A(q,:); A(q,:) <- s A(p,:) + c e^{i phi} A(q,:)
+            for (int t = tid; t < half * m; t += kJT) {
+                const int k = t / m, cl = t % m;
+                const int p = s_p[k], q = s_q[k];
+                if (q >= m) continue;
+                const double c = s_c[k], sr = s_sr[k], si = -s_si[k];  // s e^{+i phi}
+                const double s = sqrt(sr * sr + si * si);
+                const double er = s > 0.0 ? sr / s : 1.0, ei = s > 0.0 ? si / s : 0.0;
+                const double2 x = Ac[(int64_t)cl * lda + p], y = Ac[(int64_t)cl * lda + q];
+                double2 np, nq;
+                np.x = c * x.x - (sr * y.x - si * y.y);
+                np.y = c * x.y - (sr * y.y + si * y.x);
+                nq.x = s * x.x + c * (er * y.x - ei * y.y);
+                nq.y = s * x.y + c * (er * y.y + ei * y.x);
+                Ac[(int64_t)cl * lda + p] = np;
+                Ac[(int64_t)cl * lda + q] = nq;
+            }
+            __syncthreads();
+        }
+        // off-diagonal norm
+        double off = 0.0;
+        for (int t = tid; t < m * m; t += kJT) {
+            const int r = t % m, c = t / m;
+            if (r != c) {
+                const double2 v = Ac[(int64_t)c * lda + r];
+                off += v.x * v.x + v.y * v.y;
+            }
+        }
+        s_red[tid] = off;
+        __syncthreads();
+        for (int h = kJT / 2; h > 0; h >>= 1) {
+            if (tid < h) s_red[tid] += s_red[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) s_done = s_red[0] <= tol * tol * fro2 ? 1 : 0;
+        __syncthreads();
+        converged = s_done != 0;
+        __syncthreads();
+    }
+    // sort ascending (rank of each diagonal entry, ties by index), permute V
+    for (int t = tid; t < m; t += kJT) scratch[t] = Ac[(int64_t)t * lda + t].x;
+    __syncthreads();
+    for (int t = tid; t < m; t += kJT) {
+        const double d = scratch[t];
+        int rank = 0;
+        for (int u = 0; u < m; ++u) {
+            const double e = scratch[u];
+            rank += (e < d || (e == d && u < t)) ? 1 : 0;
+        }
+        w[rank] = d;
+        reinterpret_cast<int *>(scratch + m)[t] = rank;
+    }
+    __syncthreads();
+    // permuted copy of V through A's storage (A is no longer needed)
+    for (int t = tid; t < m * m; t += kJT) {
+        const int r = t % m, c = t / m;
+        const int rank = reinterpret_cast<const int *>(scratch + m)[c];
+        Ac[(int64_t)rank * lda + r] = Vc[(int64_t)c * ldv + r];
+    }
+    __syncthreads();
+    for (int t = tid; t < m * m; t += kJT) {
+        const int r = t % m, c = t / m;
+        Vc[(int64_t)c * ldv + r] = Ac[(int64_t)c * lda + r];
+    }
+    if (tid == 0) {
+        info[0] = sweep;
+        info[1] = converged ? 0 : 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small helpers of the SVQB / Rayleigh-Ritz / residual steps
+// ---------------------------------------------------------------------------
+
+// d_i = diag(S)_ii^{-1/2} (1 for non-positive entries); S <- D S D
+__global__ __launch_bounds__(kT) void svqb_scale_kernel(int m, double *S, int ld, double *d) {
+    double2 *Sc = reinterpret_cast<double2 *>(S);
+    __shared__ double sd[kMaxM];
+    for (int t = threadIdx.x; t < m; t += kT) {
+        const double v = Sc[(int64_t)t * ld + t].x;
+        sd[t] = v > 0.0 ? 1.0 / sqrt(v) : 1.0;
+        d[t] = sd[t];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * m; t += kT) {
+        const int r = t % m, c = t / m;
+        double2 v = Sc[(int64_t)c * ld + r];
+        const double f = sd[r] * sd[c];
+        v.x *= f;
+        v.y *= f;
+        Sc[(int64_t)c * ld + r] = v;
+    }
+}
+
+// T(:, c) = D V(:, first + c) / sqrt(w[first + c]), c < k (the kept directions)
+__global__ __launch_bounds__(kT) void svqb_transform_kernel(int m, int k, int first, const double *d,
+                                                            const double *V, int ldv, const double *w,
+                                                            double *T, int ldt) {
+    const double2 *Vc = reinterpret_cast<const double2 *>(V);
+    double2 *Tc = reinterpret_cast<double2 *>(T);
+    for (int t = blockIdx.x * kT + threadIdx.x; t < m * k; t += gridDim.x * kT) {
+        const int r = t % m, c = t / m;
+        const double f = d[r] / sqrt(w[first + c]);
+        double2 v = Vc[(int64_t)(first + c) * ldv + r];
+        v.x *= f;
+        v.y *= f;
+        Tc[(int64_t)c * ldt + r] = v;
+    }
+}
+
+// G <- (G + G^H) / 2
+__global__ __launch_bounds__(kT) void hermitise_kernel(int m, double *G, int ld) {
+    double2 *Gc = reinterpret_cast<double2 *>(G);
+    for (int t = blockIdx.x * kT + threadIdx.x; t < m * m; t += gridDim.x * kT) {
+        const int r = t % m, c = t / m;
+        if (r > c) continue;
+        const double2 a = Gc[(int64_t)c * ld + r], b = Gc[(int64_t)r * ld + c];
+        const double2 u = double2{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+        Gc[(int64_t)c * ld + r] = u;
+        Gc[(int64_t)r * ld + c] = double2{u.x, -u.y};
+    }
+}
+
+// Per column c of one n x nb block (blocked storage, precision prec): partial
+// sums over the rows of this workgroup of |HZ - theta_c Z|^2 and |Z|^2, written
+// to part[(2 c + q) * G + w]; reduced in order by colsum_reduce_kernel.
+__global__ __launch_bounds__(kT) void resid_partial_kernel(const void *HZ, const void *Z, int prec,
+                                                           int64_t n, int nb, const double *theta,
+                                                           double *part) {
+    __shared__ double s0[kT], s1[kT];
+    const int cpt = nb < kT ? nb : kT;           // columns handled in parallel
+    const int rows = kT / cpt;
+    const int c = threadIdx.x % cpt, rr = threadIdx.x / cpt;
+    for (int cb = 0; cb < nb; cb += cpt) {
+        const int cc = cb + c;
+        double a = 0.0, b = 0.0;
+        const double th = theta ? theta[cc] : 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * rows + rr; i < n; i += (int64_t)gridDim.x * rows) {
+            const int64_t e = i * nb + cc;
+            const double2 h = load_c(HZ, prec, e), z = load_c(Z, prec, e);
+            const double rx = h.x - th * z.x, ry = h.y - th * z.y;
+            a += rx * rx + ry * ry;
+            b += z.x * z.x + z.y * z.y;
+        }
+        s0[threadIdx.x] = a;
+        s1[threadIdx.x] = b;
+        __syncthreads();
+        if (rr == 0) {
+            double sa = 0.0, sb = 0.0;
+            for (int q = 0; q < rows; ++q) {
+                sa += s0[q * cpt + c];
+                sb += s1[q * cpt + c];
+            }
+            part[(int64_t)(2 * cc) * gridDim.x + blockIdx.x] = sa;
+            part[(int64_t)(2 * cc + 1) * gridDim.x + blockIdx.x] = sb;
+        }
+        __syncthreads();
+    }
+}
+
+// out[q] = sum_g part[q * G + g], q < count (fixed order)
+__global__ __launch_bounds__(kT) void colsum_reduce_kernel(const double *part, int G, int count,
+                                                           double *out) {
+    __shared__ double s[kT];
+    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        double a = 0.0;
+        for (int g = threadIdx.x; g < G; g += kT) a += part[(int64_t)q * G + g];
+        s[threadIdx.x] = a;
+        __syncthreads();
+        for (int h = kT / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[q] = s[0];
+        __syncthreads();
+    }
+}
+
+// Precision conversion of a blocked block vector (count complex entries).
+__global__ __launch_bounds__(kT) void convert_kernel(const void *src, int prec_src, void *dst,
+                                                     int prec_dst, int64_t count) {
+    for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < count; t += (int64_t)gridDim.x * kT)
+        store_c(dst, prec_dst, t, load_c(src, prec_src, t));
+}
+
+// SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
+__device__ inline uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Random-phase columns c in [c_begin, c_end) of a blocked block vector:
+// entry (i, c) = exp(2 pi i u), u = top 53 bits of splitmix64(k ^ i) / 2^53,
+// k = splitmix64(splitmix64(seed) ^ (col0 + c - c_begin)).
+__global__ __launch_bounds__(kT) void random_phase_kernel(void *X, int prec, int64_t n, int nb,
+                                                          int c_begin, int c_end, uint64_t seed,
+                                                          uint64_t col0) {
+    const uint64_t base = splitmix64(seed);
+    const int64_t cols = c_end - c_begin;
+    for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < n * cols;
+         t += (int64_t)gridDim.x * kT) {
+        const int64_t cc = t / n, i = t % n;
+        const uint64_t kj = splitmix64(base ^ (col0 + (uint64_t)cc));
+        const double u = (double)(splitmix64(kj ^ (uint64_t)i) >> 11) * 0x1.0p-53;
+        double sn, cs;
+        sincospi(2.0 * u, &sn, &cs);
+        store_c(X, prec, blocked_index(n, nb, i, c_begin + static_cast<int>(cc)), double2{cs, sn});
+    }
+}
+
+// Per column: index of the largest-modulus entry (ties: smallest row) and the
+// unit phase conj(z)/|z| that makes it real positive; then scale the column.
+__global__ __launch_bounds__(kT) void phase_argmax_kernel(const void *Z, int prec, int64_t n, int nb,
+                                                          int m, double *phase) {
+    __shared__ double sv[kT];
+    __shared__ int64_t si[kT];
+    for (int c = blockIdx.x; c < m; c += gridDim.x) {
+        double best = -1.0;
+        int64_t bi = 0;
+        for (int64_t i = threadIdx.x; i < n; i += kT) {
+            const double2 z = load_c(Z, prec, blocked_index(n, nb, i, c));
+            const double a = z.x * z.x + z.y * z.y;
+            if (a > best) { best = a; bi = i; }
+        }
+        sv[threadIdx.x] = best;
+        si[threadIdx.x] = bi;
+        __syncthreads();
+        for (int h = kT / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                const double o = sv[threadIdx.x + h];
+                const int64_t oi = si[threadIdx.x + h];
+                if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                    sv[threadIdx.x] = o;
+                    si[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double2 z = load_c(Z, prec, blocked_index(n, nb, si[0], c));
+            const double a = sqrt(z.x * z.x + z.y * z.y);
+            phase[2 * c] = a > 0.0 ? z.x / a : 1.0;
+            phase[2 * c + 1] = a > 0.0 ? -z.y / a : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kT) void scale_columns_kernel(void *Z, int prec, int64_t n, int nb, int m,
+                                                           const double *phase) {
+    for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < n * m; t += (int64_t)gridDim.x * kT) {
+        const int c = static_cast<int>(t / n);
+        const int64_t i = t % n;
+        const int64_t e = blocked_index(n, nb, i, c);
+        const double2 z = load_c(Z, prec, e);
+        const double pr = phase[2 * c], pi = phase[2 * c + 1];
+        store_c(Z, prec, e, double2{z.x * pr - z.y * pi, z.x * pi + z.y * pr});
+    }
+}
+
+}  // namespace
+
+int launch_gram(const void *A, const void *B, int prec, int64_t n, int nb, int m1, int m2,
+                double *part, int nsplit, double *S, int ld, hipStream_t s) {
+    const int ta = (m1 + kGT - 1) / kGT, tb = (m2 + kGT - 1) / kGT;
+    const int64_t rps = ((n + nsplit - 1) / nsplit + kGK - 1) / kGK * kGK;
+    hipLaunchKernelGGL(gram_kernel, dim3(ta * tb, nsplit), dim3(kT), 0, s, A, B, prec, n, nb, m1, m2,
+                       ta, tb, rps, part);
+    CHEBFD_HIP(hipGetLastError());
+    const int64_t total = (int64_t)ta * tb * kGT * kGT;
+    int G = static_cast<int>((total + kT - 1) / kT);
+    if (G > 4096) G = 4096;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(G), dim3(kT), 0, s, part, nsplit, ta * tb, ta, m1, m2,
+                       S, ld);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+size_t gram_part_bytes(int m1, int m2, int nsplit) {
+    const size_t ta = (m1 + kGT - 1) / kGT, tb = (m2 + kGT - 1) / kGT;
+    return ta * tb * (size_t)nsplit * kGT * kGT * 16;
+}
+
+int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm, void *Z, int prec_z,
+                  int nb_z, int64_t n, int m1, int m2, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>((n + kGT - 1) / kGT), (m2 + kGT - 1) / kGT);
+    hipLaunchKernelGGL(update_kernel, grid, dim3(kT), 0, s, A, prec_a, nb_a, M, ldm, Z, prec_z, nb_z,
+                       n, m1, m2);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int launch_jacobi(int m, double *A, int lda, double *V, int ldv, double *w, int max_sweeps,
+                  double tol, int *info, double *scratch, hipStream_t s) {
+    if (m > kMaxM) CHEBFD_FAIL(CHEBFD_EINVAL, "eigensolver size %d > %d", m, kMaxM);
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJT), 0, s, m, A, lda, V, ldv, w, max_sweeps, tol,
+                       info, scratch);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+static int grid_cap(int64_t work, int cap = 8192) {
+    int64_t g = (work + kT - 1) / kT;
+    if (g > cap) g = cap;
+    return static_cast<int>(g < 1 ? 1 : g);
+}
+
+int launch_svqb_scale(int m, double *S, int ld, double *d, hipStream_t s) {
+    if (m > kMaxM) CHEBFD_FAIL(CHEBFD_EINVAL, "SVQB size %d > %d", m, kMaxM);
+    hipLaunchKernelGGL(svqb_scale_kernel, dim3(1), dim3(kT), 0, s, m, S, ld, d);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int launch_svqb_transform(int m, int k, int first, const double *d, const double *V, int ldv,
+                          const double *w, double *T, int ldt, hipStream_t s) {
+    hipLaunchKernelGGL(svqb_transform_kernel, dim3(grid_cap((int64_t)m * k)), dim3(kT), 0, s, m, k,
+                       first, d, V, ldv, w, T, ldt);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int launch_hermitise(int m, double *G, int ld, hipStream_t s) {
+    hipLaunchKernelGGL(hermitise_kernel, dim3(grid_cap((int64_t)m * m)), dim3(kT), 0, s, m, G, ld);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int resid_grid(int64_t n) { return grid_cap(n, 1024); }
+
+int launch_resid(const void *HZ, const void *Z, int prec, int64_t n, int nb, const double *theta,
+                 double *part, int G, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(resid_partial_kernel, dim3(G), dim3(kT), 0, s, HZ, Z, prec, n, nb, theta, part);
+    CHEBFD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3(2 * nb), dim3(kT), 0, s, part, G, 2 * nb, out);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int launch_convert(const void *src, int prec_src, void *dst, int prec_dst, int64_t count,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(convert_kernel, dim3(grid_cap(count, 65536)), dim3(kT), 0, s, src, prec_src, dst,
+                       prec_dst, count);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int launch_random_phase(void *X, int prec, int64_t n, int nb, int c_begin, int c_end, uint64_t seed,
+                        uint64_t col0, hipStream_t s) {
+    if (c_end <= c_begin) return CHEBFD_OK;
+    hipLaunchKernelGGL(random_phase_kernel, dim3(grid_cap(n * (c_end - c_begin), 65536)), dim3(kT), 0, s,
+                       X, prec, n, nb, c_begin, c_end, seed, col0);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int launch_fix_phases(void *Z, int prec, int64_t n, int nb, int m, double *phase, hipStream_t s) {
+    hipLaunchKernelGGL(phase_argmax_kernel, dim3(m < 1024 ? m : 1024), dim3(kT), 0, s, Z, prec, n, nb, m,
+                       phase);
+    CHEBFD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(scale_columns_kernel, dim3(grid_cap(n * m, 65536)), dim3(kT), 0, s, Z, prec, n, nb,
+                       m, phase);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+}  // namespace chebfd

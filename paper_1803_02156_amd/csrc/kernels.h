@@ -17,6 +17,7 @@ enum { kModeFirst = 0, kModeSecond = 1, kModeStep = 2, kModeKpm = 3 };
 
 struct StepArgs {
     int64_t n;
+    int64_t n_chunks;
     int64_t npass;              // ceil(n / (256 / NB)) row passes
     const int64_t *chunk_off;
     const int32_t *chunk_width;
@@ -35,12 +36,57 @@ struct StepArgs {
     double *red_eta;            // destination of the reduced eta (re, im pairs) [NB]
     double *red_nu;             // destination of the reduced nu [NB]
     int32_t G_prev;
-    int32_t pad;
+    int32_t uniform_width;      // every chunk has this many slots per row (0: read chunk_width)
 };
 
 int launch_step(int prec, int nb, int mode, const StepArgs &a, int G, hipStream_t s);
+
+// LDS-staged step kernel (filter_lds.hip): tiles of whole SELL chunks
+struct LdsGeometry {
+    int tile_rows;      // rows per tile: max(C, 256 / n_b)
+    int tile_slots;     // LDS slots per tile buffer: max_width * tile_rows
+    int maxw;           // compile-time row width of the kernel instance (13 or 16)
+    int G;              // persistent grid
+    int64_t ntiles;
+    size_t lds_bytes;
+};
+bool lds_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, LdsGeometry *g);
+int launch_lds_step(int prec, int nb, int mode, const StepArgs &a, const LdsGeometry &g,
+                    hipStream_t s);
+// row-per-wavefront kernel for n_b in {32, 64, 128}: a pass covers 128 / n_b rows
+// Rows up to kRowMaxUnrolled stored entries use the unrolled path, whose loads
+// may read up to kRowMaxUnrolled * C slots past the last chunk: the matrix
+// buffer carries that many zero slots as padding.
+constexpr int kRowMaxUnrolled = 16;
+int launch_row_step(int prec, int nb, int max_width, int mode, const StepArgs &a, int G,
+                    hipStream_t s);
+int row_occupancy(int prec, int nb);
+constexpr int kRowKernelMinNb = 32;
+inline int row_kernel_rows_per_pass(int nb) { return 128 / nb; }
 int launch_reduce(int nb, const StepArgs &a, hipStream_t s);
 int step_grid(int prec, int nb, int64_t npass, int num_cus);
+
+// dense kernels (dense.hip)
+int launch_gram(const void *A, const void *B, int prec, int64_t n, int nb, int m1, int m2,
+                double *part, int nsplit, double *S, int ld, hipStream_t s);
+size_t gram_part_bytes(int m1, int m2, int nsplit);
+int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm, void *Z, int prec_z,
+                  int nb_z, int64_t n, int m1, int m2, hipStream_t s);
+int launch_jacobi(int m, double *A, int lda, double *V, int ldv, double *w, int max_sweeps,
+                  double tol, int *info, double *scratch, hipStream_t s);
+
+int launch_svqb_scale(int m, double *S, int ld, double *d, hipStream_t s);
+int launch_svqb_transform(int m, int k, int first, const double *d, const double *V, int ldv,
+                          const double *w, double *T, int ldt, hipStream_t s);
+int launch_hermitise(int m, double *G, int ld, hipStream_t s);
+int resid_grid(int64_t n);
+int launch_resid(const void *HZ, const void *Z, int prec, int64_t n, int nb, const double *theta,
+                 double *part, int G, double *out, hipStream_t s);
+int launch_convert(const void *src, int prec_src, void *dst, int prec_dst, int64_t count,
+                   hipStream_t s);
+int launch_random_phase(void *X, int prec, int64_t n, int nb, int c_begin, int c_end, uint64_t seed,
+                        uint64_t col0, hipStream_t s);
+int launch_fix_phases(void *Z, int prec, int64_t n, int nb, int m, double *phase, hipStream_t s);
 
 // layout / misc kernels (layout.hip)
 int launch_pack(const int32_t *perm, int64_t n, int m, int nb, int prec, const void *src,
