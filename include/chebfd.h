@@ -173,6 +173,112 @@ int chebfd_op(const chebfd_matrix *H, double alpha, double beta, double gamma, i
               size_t work_bytes, void *stream);
 
 /*
+ * Sparse matrix times one block (Alg. 1 line 4, spmmv()): Y = (alpha H + beta I) X
+ * for an n x n_b block in the blocked layout and the matrix's precision.
+ * d_work: chebfd_filter_query bytes.  X and Y must not overlap.
+ */
+int chebfd_spmmv(const chebfd_matrix *H, double alpha, double beta, int32_t n_b, int32_t prec,
+                 const void *d_x, void *d_y, void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * Kernel polynomial method moments (Sect. 2, the density-of-states and
+ * eigenvalue-count estimate that Alg. 1's dot products feed): R random-phase
+ * vectors x^(r) (|x_i| = 1, drawn on the device from `seed` with the same
+ * counter-based generator as chebfd_solve's start block, columns 0..R-1) are
+ * run through the Chebyshev recurrence of H~ = alpha H + beta I for n_steps
+ * steps without forming a filtered block, and
+ *   h_mu[m] = (1 / (n R)) sum_r Re <x^(r), T_m(H~) x^(r)>,  m = 0 .. 2 n_steps - 1
+ * is returned on the host (h_mu: 2 n_steps doubles), the moments of order >=
+ * n_steps + 1 from the product rule T_k T_k = (T_2k + T_0) / 2 and
+ * T_{k+1} T_k = (T_2k+1 + T_1) / 2.  h_mu[0] is 1 up to rounding.
+ * R: a power of two up to 32 or a multiple of 32 (blocks of min(R, 32)).
+ * n_steps >= 1.  Precision: the matrix's (FP64 accumulation of the products).
+ * d_work: chebfd_kpm_query bytes, 256-byte aligned.  Synchronises the stream.
+ */
+int chebfd_kpm_query(const chebfd_matrix *H, int32_t n_steps, int32_t R, size_t *work_bytes);
+int chebfd_kpm_moments(const chebfd_matrix *H, double alpha, double beta, int32_t n_steps, int32_t R,
+                       uint64_t seed, double *h_mu, void *d_work, size_t work_bytes, void *stream);
+
+/*
+ * Tall-skinny Gram product S = A^H B (FP64 complex, S column-major with leading
+ * dimension ld >= m1) of two n x m1 and n x m2 block vectors in the blocked
+ * layout (block width n_b, precision prec), with FP64 MFMA; the row range is
+ * split over workgroups and the partial products are summed in a fixed order.
+ * d_work: chebfd_gram_query bytes.
+ */
+int chebfd_gram_query(int64_t n, int32_t m1, int32_t m2, size_t *work_bytes);
+int chebfd_gram(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec, const void *d_a,
+                const void *d_b, double *d_s, int32_t ld, void *d_work, size_t work_bytes,
+                void *stream);
+
+/*
+ * Tall-skinny update Z = A M: A n x m1 (blocked, precision prec_a), M m1 x m2 FP64
+ * complex column-major (ldm), Z n x m2 (blocked, precision prec_z), FP64 MFMA.
+ * A and Z must not overlap.
+ */
+int chebfd_update(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec_a, const void *d_a,
+                  const double *d_m, int32_t ldm, int32_t prec_z, void *d_z, void *stream);
+
+/*
+ * Eigendecomposition of a Hermitian m x m FP64 complex matrix (m <= 512) by
+ * cyclic Jacobi rotations in one workgroup: d_w receives the eigenvalues in
+ * ascending order, d_v (ldv) the eigenvectors; d_a (lda) is overwritten.
+ * Synchronises `stream`; CHEBFD_ENUMERIC if 40 sweeps do not reduce the
+ * off-diagonal Frobenius norm below 2^-52 of the matrix's.
+ */
+int chebfd_heev_query(int32_t m, size_t *work_bytes);
+int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, double *d_w,
+                void *d_work, size_t work_bytes, void *stream, int32_t *h_sweeps);
+
+/*
+ * The ChebFD iteration (Sect. 2): filter the search block, orthonormalise it by
+ * SVQB twice (rank revealing: Gram eigenvalues below
+ * max(100 eps, (10 eps_store)^2) times the largest are dropped), Rayleigh-Ritz on
+ * the kept directions, residuals in FP64, restart from the Ritz vectors plus
+ * fresh random-phase vectors in place of dropped directions.
+ * A Ritz pair inside the closed interval [lam_L, lam_R] is converged if its
+ * residual ||H z - theta z|| (||z|| = 1) is <= tol and spurious if its residual
+ * exceeds (lam_R - lam_L) / 2; the iteration stops when the number of converged
+ * pairs repeats and every pair in the interval is converged or spurious
+ * (status CHEBFD_OK), after max_iter iterations (CHEBFD_NOT_CONVERGED), or when
+ * more than 3/4 n_s Ritz values fall in the interval (CHEBFD_SUBSPACE_SMALL).
+ *
+ * H is the filter's matrix (precision p->prec); H64 an FP64 copy of the same
+ * matrix (same n, C, sigma) for the Rayleigh-Ritz products and residuals (may
+ * be H itself when p->prec is FP64).  d_x0: n x n_s c128 column-major start
+ * block, or NULL for random phases exp(2 pi i u) with u from SplitMix64
+ * (seed p->seed; the same vectors as topi.random_phase_block).  Refill vectors
+ * of iteration k use the same generator with column offset k n_s.
+ * Outputs: h_theta[n_s] and h_resid[n_s]: the converged pairs first (ascending),
+ * then the other Ritz values (ascending); d_Z (n x n_s c128 column-major, may be
+ * NULL): the Ritz vectors in the same order, each scaled so that its largest
+ * entry is real positive; columns beyond the kept directions are zero.
+ */
+typedef struct chebfd_params {
+    double lam_L, lam_R;   /* closed search interval, H's units */
+    int32_t n_s, n_p, n_b; /* subspace size (multiple of n_b), filter degree, block width */
+    int32_t prec;          /* CHEBFD_PREC_* of the filter */
+    double tol;            /* residual tolerance */
+    int32_t max_iter;
+    int32_t reserved;
+    uint64_t seed;
+    double spec_lo, spec_hi; /* spectral bounds of H; NaN for Gershgorin bounds */
+} chebfd_params;
+
+typedef struct chebfd_stats {
+    int32_t iterations, n_found, n_kept, status;
+    double count_est;       /* eigenvalue count estimate from the first filter's moments */
+    double t_total, t_filter, t_orth, t_rr, t_resid;  /* seconds (HIP events) */
+    double filter_bytes;    /* algorithmic bytes of all filter applications */
+} chebfd_stats;
+
+int chebfd_solve_query(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_params *p,
+                       size_t *work_bytes);
+int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_params *p,
+                 const void *d_x0, void *d_work, size_t work_bytes, void *stream, int32_t *n_found,
+                 double *h_theta, void *d_Z, double *h_resid, chebfd_stats *st);
+
+/*
  * HBM bandwidth probe (the STREAM analogue of Sect. 1.2, Table 2): copy
  * (b = a) or triad (a = b + s c) over `count` doubles.  kind 0 = copy,
  * kind 1 = triad.

@@ -25,7 +25,25 @@ class ChebfdMatrix(ctypes.Structure):
     ]
 
 
+class ChebfdParams(ctypes.Structure):
+    _fields_ = [
+        ("lam_L", f64), ("lam_R", f64), ("n_s", i32), ("n_p", i32), ("n_b", i32), ("prec", i32),
+        ("tol", f64), ("max_iter", i32), ("reserved", i32), ("seed", ctypes.c_uint64),
+        ("spec_lo", f64), ("spec_hi", f64),
+    ]
+
+
+class ChebfdStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", i32), ("n_found", i32), ("n_kept", i32), ("status", i32),
+        ("count_est", f64), ("t_total", f64), ("t_filter", f64), ("t_orth", f64), ("t_rr", f64),
+        ("t_resid", f64), ("filter_bytes", f64),
+    ]
+
+
 MP = ctypes.POINTER(ChebfdMatrix)
+PP = ctypes.POINTER(ChebfdParams)
+SP = ctypes.POINTER(ChebfdStats)
 DP = ctypes.POINTER(f64)
 
 # name -> (restype, argtypes); every symbol the header declares
@@ -43,6 +61,16 @@ SIGNATURES = {
     "chebfd_filter_query": (ctypes.c_int, [MP, i32, ctypes.POINTER(sz)]),
     "chebfd_filter": (ctypes.c_int, [MP, f64, f64, P, i32, i32, i32, i32, P, P, P, P, P, P, sz, P]),
     "chebfd_op": (ctypes.c_int, [MP, f64, f64, f64, i32, i32, P, P, P, P, sz, P]),
+    "chebfd_spmmv": (ctypes.c_int, [MP, f64, f64, i32, i32, P, P, P, sz, P]),
+    "chebfd_kpm_query": (ctypes.c_int, [MP, i32, i32, ctypes.POINTER(sz)]),
+    "chebfd_kpm_moments": (ctypes.c_int, [MP, f64, f64, i32, i32, ctypes.c_uint64, DP, P, sz, P]),
+    "chebfd_gram_query": (ctypes.c_int, [i64, i32, i32, ctypes.POINTER(sz)]),
+    "chebfd_gram": (ctypes.c_int, [i64, i32, i32, i32, i32, P, P, P, i32, P, sz, P]),
+    "chebfd_update": (ctypes.c_int, [i64, i32, i32, i32, i32, P, P, i32, i32, P, P]),
+    "chebfd_heev_query": (ctypes.c_int, [i32, ctypes.POINTER(sz)]),
+    "chebfd_heev": (ctypes.c_int, [i32, P, i32, P, i32, P, P, sz, P, ctypes.POINTER(i32)]),
+    "chebfd_solve_query": (ctypes.c_int, [MP, MP, PP, ctypes.POINTER(sz)]),
+    "chebfd_solve": (ctypes.c_int, [MP, MP, PP, P, P, sz, P, ctypes.POINTER(i32), P, P, P, SP]),
     "chebfd_probe_stream": (ctypes.c_int, [i32, i64, P, P, f64, P, P]),
 }
 

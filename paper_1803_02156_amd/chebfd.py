@@ -182,3 +182,106 @@ def chebfd_op(H: Matrix, alpha: float, beta: float, gamma: float, n_b: int, u, w
 def chebfd_probe_stream(kind: int, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor | None = None,
                         s: float = 3.0):
     check(load().chebfd_probe_stream(kind, a.numel(), _ptr(b), _ptr(c), s, _ptr(a), _stream()))
+
+
+def chebfd_spmmv(H: Matrix, alpha: float, beta: float, x: torch.Tensor, y: torch.Tensor | None = None):
+    """y = (alpha H + beta I) x for one blocked block x of shape (n, n_b) (or (1, n, n_b))."""
+    n_b = x.shape[-1]
+    if y is None:
+        y = torch.empty_like(x)
+    nbytes = chebfd_filter_query(H, n_b)
+    work = device_buffer(nbytes, x.device)
+    check(load().chebfd_spmmv(H.ref(), alpha, beta, n_b, H.prec, _ptr(x), _ptr(y), _ptr(work), nbytes,
+                              _stream()))
+    return y
+
+
+def chebfd_kpm_moments(H: Matrix, alpha: float, beta: float, n_steps: int, R: int, seed: int = 0):
+    """Averaged KPM moments mu_0 .. mu_{2 n_steps - 1} of alpha H + beta I from R
+    device-drawn random-phase vectors (numpy float64 array)."""
+    sz = ctypes.c_size_t()
+    check(load().chebfd_kpm_query(H.ref(), n_steps, R, ctypes.byref(sz)))
+    work = device_buffer(sz.value, H.buf.device)
+    mu = np.empty(2 * n_steps, dtype=np.float64)
+    check(load().chebfd_kpm_moments(H.ref(), alpha, beta, n_steps, R, seed,
+                                    mu.ctypes.data_as(_abi.DP), _ptr(work), sz.value, _stream()))
+    return mu
+
+
+def chebfd_gram(a: torch.Tensor, b: torch.Tensor, m1: int | None = None, m2: int | None = None):
+    """S = A^H B for blocked tensors a (n_blocks, n, n_b) and b of the same precision and n_b."""
+    nblk, n, n_b = a.shape
+    m1 = nblk * n_b if m1 is None else m1
+    m2 = b.shape[0] * n_b if m2 is None else m2
+    prec = PREC_FP64 if a.dtype == torch.complex128 else PREC_MIXED
+    sz = ctypes.c_size_t()
+    check(load().chebfd_gram_query(n, m1, m2, ctypes.byref(sz)))
+    work = device_buffer(sz.value, a.device)
+    S = torch.zeros((m2, m1), dtype=torch.complex128, device=a.device)   # column-major m1 x m2
+    check(load().chebfd_gram(n, n_b, m1, m2, prec, _ptr(a), _ptr(b), _ptr(S), m1, _ptr(work), sz.value,
+                             _stream()))
+    return S.T
+
+
+def chebfd_update(a: torch.Tensor, M: torch.Tensor, prec_z: int | None = None):
+    """Z = A M for a blocked tensor a (n_blocks, n, n_b) and a complex128 (m1, m2) matrix M."""
+    nblk, n, n_b = a.shape
+    m1, m2 = M.shape
+    prec_a = PREC_FP64 if a.dtype == torch.complex128 else PREC_MIXED
+    prec_z = prec_a if prec_z is None else prec_z
+    Mc = M.to(torch.complex128).T.contiguous()      # column-major
+    z = torch.zeros(((m2 + n_b - 1) // n_b, n, n_b), dtype=vec_dtype(prec_z), device=a.device)
+    check(load().chebfd_update(n, n_b, m1, m2, prec_a, _ptr(a), _ptr(Mc), m1, prec_z, _ptr(z), _stream()))
+    return z
+
+
+def chebfd_heev(A: torch.Tensor):
+    """Eigenvalues (ascending) and eigenvectors of a Hermitian complex128 CUDA matrix."""
+    m = A.shape[0]
+    a = A.to(torch.complex128).T.contiguous()        # column-major copy (overwritten)
+    v = torch.empty_like(a)
+    w = torch.empty(m, dtype=torch.float64, device=A.device)
+    sz = ctypes.c_size_t()
+    check(load().chebfd_heev_query(m, ctypes.byref(sz)))
+    work = device_buffer(sz.value, A.device)
+    sweeps = ctypes.c_int32()
+    check(load().chebfd_heev(m, _ptr(a), m, _ptr(v), m, _ptr(w), _ptr(work), sz.value, _stream(),
+                             ctypes.byref(sweeps)))
+    return w, v.T, sweeps.value
+
+
+class SolveResult:
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    def __repr__(self):
+        return (f"SolveResult(status={self.status}, iterations={self.stats.iterations}, "
+                f"n_found={self.n_found})")
+
+
+def chebfd_solve(H: Matrix, H64: Matrix, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
+                 tol: float | None = None, max_iter: int = 50, seed: int = 0, x0: torch.Tensor | None = None,
+                 spec_bounds=None, want_vectors: bool = True):
+    """Run the device ChebFD iteration; returns theta, residuals, Ritz vectors (column-major c128)."""
+    prec = H.prec
+    if tol is None:
+        tol = 1e-9 if prec == PREC_FP64 else 1e-7
+    p = _abi.ChebfdParams()
+    p.lam_L, p.lam_R, p.n_s, p.n_p, p.n_b, p.prec = lam_L, lam_R, n_s, n_p, n_b, prec
+    p.tol, p.max_iter, p.seed = tol, max_iter, seed
+    p.spec_lo, p.spec_hi = (float("nan"), float("nan")) if spec_bounds is None else spec_bounds
+    sz = ctypes.c_size_t()
+    check(load().chebfd_solve_query(H.ref(), H64.ref(), ctypes.byref(p), ctypes.byref(sz)))
+    work = device_buffer(sz.value, H.buf.device)
+    if x0 is not None:
+        _colmajor_ok(x0, H.n)
+    Z = torch.empty((n_s, H.n), dtype=torch.complex128, device=H.buf.device).T if want_vectors else None
+    theta = np.empty(n_s)
+    resid = np.empty(n_s)
+    nf = ctypes.c_int32()
+    st = _abi.ChebfdStats()
+    rc = check(load().chebfd_solve(H.ref(), H64.ref(), ctypes.byref(p), _ptr(x0), _ptr(work), sz.value,
+                                   _stream(), ctypes.byref(nf), theta.ctypes.data_as(ctypes.c_void_p),
+                                   _ptr(Z), resid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+    return SolveResult(status=rc, n_found=nf.value, theta=theta, resid=resid, Z=Z, stats=st,
+                       workspace_bytes=sz.value)

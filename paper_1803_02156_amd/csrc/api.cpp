@@ -465,6 +465,11 @@ static StepArgs base_args(const chebfd_matrix *H, double alpha, double beta) {
     return a;
 }
 
+static int filter_run(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma, int n_p,
+                      int n_s, int n_b, int prec, void *d_xy, void *d_u, void *d_w, double *d_eta,
+                      double *d_nu, void *d_work, size_t need, const StepGeometry &geo, bool moments_only,
+                      hipStream_t s);
+
 int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
                   int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
                   void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,
@@ -500,7 +505,20 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
         CHEBFD_REQUIRE(!overlap(d_eta, 2 * mb, d_nu, mb), "d_eta and d_nu overlap");
     }
 
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return filter_run(H, alpha, beta, h_gamma, n_p, n_s, n_b, prec, d_xy, d_u, d_w, d_eta, d_nu, d_work, need,
+                      geo, false, static_cast<hipStream_t>(stream));
+}
+
+// The filter driver shared by chebfd_filter and chebfd_kpm_moments (arguments
+// validated by the caller).  moments_only: Alg. 1 without the filtered-block
+// update (the KPM moments); X is then overwritten by Chebyshev vectors.
+static int filter_run(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma, int n_p,
+                      int n_s, int n_b, int prec, void *d_xy, void *d_u, void *d_w, double *d_eta,
+                      double *d_nu, void *d_work, size_t need, const StepGeometry &geo, bool moments_only,
+                      hipStream_t s) {
+    int rc;
+    const int G = geo.G;
+    const size_t blk = vec_elem_bytes(prec) * (size_t)H->n * n_b;
     double *part[2];
     part[0] = static_cast<double *>(d_work);
     part[1] = reinterpret_cast<double *>(static_cast<char *>(d_work) + need / 2);
@@ -534,7 +552,9 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
         char *X = static_cast<char *>(d_xy) + blk * b;
         void *A = d_u, *B = d_w;
         if (n_p == 0) {
-            if ((rc = launch_axpby_blocked(prec, count, h_gamma[0], X, 0.0, nullptr, s))) return rc;
+            if (!moments_only &&
+                (rc = launch_axpby_blocked(prec, count, h_gamma[0], X, 0.0, nullptr, s)))
+                return rc;
             continue;
         }
         StepArgs a = base_args(H, alpha, beta);
@@ -542,6 +562,18 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
         a.P = X;
         a.N = A;
         if ((rc = launch_any(H, prec, n_b, kModeFirst, next_args(a, 1, b), geo, s))) return rc;
+        if (moments_only) {
+            // X <- 2(aH + bI) U - X = T_2 x, then alternate in place (no Y)
+            void *cur = A, *prv = X;
+            for (int p = 2; p <= n_p; ++p) {
+                a = base_args(H, alpha, beta);
+                a.P = cur;
+                a.O = prv;
+                if ((rc = launch_any(H, prec, n_b, kModeKpm, next_args(a, p, b), geo, s))) return rc;
+                std::swap(cur, prv);
+            }
+            continue;
+        }
         if (n_p == 1) {
             if ((rc = launch_axpby_blocked(prec, count, h_gamma[0], X, h_gamma[1], A, s))) return rc;
             continue;
@@ -580,6 +612,91 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
     return CHEBFD_OK;
 }
 
+// KPM workspace: X (R vectors, blocked by n_b = min(R, 32)), U, eta, nu and the
+// filter partials, each 256-byte aligned.  Moments-only runs need no W block.
+struct KpmLayout {
+    size_t x, u, eta, nu, part, filter_bytes, total;
+};
+
+static int kpm_layout(const chebfd_matrix *H, int n_steps, int R, StepGeometry *geo, KpmLayout *L) {
+    int rc;
+    if ((rc = check_handle(H))) return rc;
+    CHEBFD_REQUIRE(n_steps >= 1, "n_steps = %d < 1", n_steps);
+    CHEBFD_REQUIRE(R >= 1 && ((R <= 32 && (R & (R - 1)) == 0) || R % 32 == 0),
+                   "R = %d must be a power of two up to 32 or a multiple of 32", R);
+    const int n_b = R < 32 ? R : 32;
+    if ((rc = filter_geometry(H, H->prec, n_b, geo))) return rc;
+    L->filter_bytes = filter_work_bytes(n_b, geo->G);
+    const size_t sw = vec_elem_bytes(H->prec), n = H->n;
+    size_t at = 0;
+    auto take = [&](size_t b) { size_t h = at; at = round_up(at + b, 256); return h; };
+    L->x = take(n * R * sw);
+    L->u = take(n * n_b * sw);
+    L->eta = take(sizeof(double) * 2 * (size_t)(n_steps + 1) * R);
+    L->nu = take(sizeof(double) * (size_t)(n_steps + 1) * R);
+    L->part = take(L->filter_bytes);
+    L->total = at;
+    return CHEBFD_OK;
+}
+
+int chebfd_kpm_query(const chebfd_matrix *H, int32_t n_steps, int32_t R, size_t *work_bytes) {
+    clear_error();
+    CHEBFD_REQUIRE(work_bytes != nullptr, "work_bytes is NULL");
+    StepGeometry geo;
+    KpmLayout L;
+    int rc = kpm_layout(H, n_steps, R, &geo, &L);
+    if (rc) return rc;
+    *work_bytes = L.total;
+    return CHEBFD_OK;
+}
+
+int chebfd_kpm_moments(const chebfd_matrix *H, double alpha, double beta, int32_t n_steps, int32_t R,
+                       uint64_t seed, double *h_mu, void *d_work, size_t work_bytes, void *stream) {
+    clear_error();
+    StepGeometry geo;
+    KpmLayout L;
+    int rc = kpm_layout(H, n_steps, R, &geo, &L);
+    if (rc) return rc;
+    CHEBFD_REQUIRE(h_mu != nullptr, "h_mu is NULL");
+    CHEBFD_REQUIRE(std::isfinite(alpha) && std::isfinite(beta), "alpha/beta not finite");
+    CHEBFD_REQUIRE(d_work && aligned(d_work, 256), "d_work must be non-NULL and 256-byte aligned");
+    if (work_bytes < L.total) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "KPM workspace %zu < %zu", work_bytes, L.total);
+    const int n_b = R < 32 ? R : 32;
+    const int prec = H->prec;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(d_work);
+    double *eta = reinterpret_cast<double *>(w + L.eta), *nu = reinterpret_cast<double *>(w + L.nu);
+    if ((rc = launch_random_phase(w + L.x, prec, H->n, n_b, 0, R, seed, 0,
+                                  H->identity_perm ? nullptr : H->perm, s)))
+        return rc;
+    // W is never touched by a moments-only run; U stands in for it
+    if ((rc = filter_run(H, alpha, beta, nullptr, n_steps, R, n_b, prec, w + L.x, w + L.u, w + L.u, eta, nu,
+                         w + L.part, L.filter_bytes, geo, true, s)))
+        return rc;
+    std::vector<double> he(2 * (size_t)(n_steps + 1) * R), hn((size_t)(n_steps + 1) * R);
+    CHEBFD_HIP(hipMemcpyAsync(he.data(), eta, sizeof(double) * he.size(), hipMemcpyDeviceToHost, s));
+    CHEBFD_HIP(hipMemcpyAsync(hn.data(), nu, sizeof(double) * hn.size(), hipMemcpyDeviceToHost, s));
+    CHEBFD_HIP(hipStreamSynchronize(s));
+    // Column sums of eta_q = <T_q x, T_{q-1} x> and nu_q = <T_{q-1} x, T_{q-1} x>,
+    // then the product rule: mu_0 = nu_1, mu_1 = eta_1, mu_2k = 2 nu_{k+1} - mu_0,
+    // mu_{2k+1} = 2 eta_{k+1} - mu_1.  Real parts: H is Hermitian.
+    std::vector<double> se(n_steps + 1, 0.0), sn(n_steps + 1, 0.0);
+    for (int q = 1; q <= n_steps; ++q)
+        for (int j = 0; j < R; ++j) {
+            se[q] += he[2 * ((size_t)q * R + j)];
+            sn[q] += hn[(size_t)q * R + j];
+        }
+    const double scale = 1.0 / ((double)H->n * R);
+    const double mu0 = sn[1], mu1 = se[1];
+    h_mu[0] = mu0 * scale;
+    h_mu[1] = mu1 * scale;
+    for (int k = 1; k < n_steps; ++k) {
+        h_mu[2 * k] = (2.0 * sn[k + 1] - mu0) * scale;
+        h_mu[2 * k + 1] = (2.0 * se[k + 1] - mu1) * scale;
+    }
+    return CHEBFD_OK;
+}
+
 int chebfd_op(const chebfd_matrix *H, double alpha, double beta, double gamma, int32_t n_b,
               int32_t prec, const void *d_u, void *d_w, void *d_y, void *d_work, size_t work_bytes,
               void *stream) {
@@ -605,6 +722,29 @@ int chebfd_op(const chebfd_matrix *H, double alpha, double beta, double gamma, i
     a.g2 = gamma;
     a.part_out = static_cast<double *>(d_work);
     return launch_any(H, prec, n_b, kModeStep, a, geo, static_cast<hipStream_t>(stream));
+}
+
+int chebfd_spmmv(const chebfd_matrix *H, double alpha, double beta, int32_t n_b, int32_t prec,
+                 const void *d_x, void *d_y, void *d_work, size_t work_bytes, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(prec, n_b))) return rc;
+    CHEBFD_REQUIRE(prec == H->prec, "prec %d differs from the matrix's %d", prec, H->prec);
+    CHEBFD_REQUIRE(d_x && d_y && d_work, "NULL device buffer");
+    CHEBFD_REQUIRE(std::isfinite(alpha) && std::isfinite(beta), "alpha/beta not finite");
+    const size_t blk = vec_elem_bytes(prec) * (size_t)H->n * n_b;
+    StepGeometry geo;
+    if ((rc = filter_geometry(H, prec, n_b, &geo))) return rc;
+    const size_t need = filter_work_bytes(n_b, geo.G);
+    if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "workspace %zu < %zu", work_bytes, need);
+    CHEBFD_REQUIRE(!overlap(d_x, blk, d_y, blk) && !overlap(d_work, need, d_x, blk) &&
+                       !overlap(d_work, need, d_y, blk),
+                   "buffers overlap");
+    StepArgs a = base_args(H, alpha, beta);
+    a.P = d_x;
+    a.N = d_y;
+    a.part_out = static_cast<double *>(d_work);
+    return launch_any(H, prec, n_b, kModeFirst, a, geo, static_cast<hipStream_t>(stream));
 }
 
 int chebfd_probe_stream(int32_t kind, int64_t count, const double *d_b, const double *d_c, double s,

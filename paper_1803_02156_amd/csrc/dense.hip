@@ -61,9 +61,9 @@ __device__ inline int64_t blocked_index(int64_t n, int nb, int64_t i, int c) {
 constexpr int kGT = 64;   // output tile edge
 constexpr int kGK = 16;   // rows per LDS stage
 
-__global__ __launch_bounds__(kT) void gram_kernel(const void *A, const void *B, int prec, int64_t n,
-                                                   int nb, int m1, int m2, int tiles_a,
-                                                   int tiles_b, int64_t rows_per_split,
+__global__ __launch_bounds__(kT) void gram_kernel(const void *A, int prec_a, int nb_a, const void *B,
+                                                   int prec_b, int nb_b, int64_t n, int m1, int m2,
+                                                   int tiles_a, int tiles_b, int64_t rows_per_split,
                                                    double *part) {
     __shared__ double2 sa[kGK][kGT];
     __shared__ double2 sb[kGK][kGT];
@@ -93,8 +93,8 @@ __global__ __launch_bounds__(kT) void gram_kernel(const void *A, const void *B, 
             const int64_t i = rb + rr;
             double2 va = {0.0, 0.0}, vb = {0.0, 0.0};
             if (i < r1) {
-                if (a0 + cc < m1) va = load_c(A, prec, blocked_index(n, nb, i, a0 + cc));
-                if (b0 + cc < m2) vb = load_c(B, prec, blocked_index(n, nb, i, b0 + cc));
+                if (a0 + cc < m1) va = load_c(A, prec_a, blocked_index(n, nb_a, i, a0 + cc));
+                if (b0 + cc < m2) vb = load_c(B, prec_b, blocked_index(n, nb_b, i, b0 + cc));
             }
             sa[rr][cc] = va;
             sb[rr][cc] = vb;
@@ -521,6 +521,17 @@ __global__ __launch_bounds__(kT) void colsum_reduce_kernel(const double *part, i
     }
 }
 
+// T(:, c) = S(:, order[c]) for c < m (FP64 complex, column-major)
+__global__ __launch_bounds__(kT) void permute_columns_kernel(int rows, int m, const double *S, int lds,
+                                                             const int *order, double *T, int ldt) {
+    const double2 *Sc = reinterpret_cast<const double2 *>(S);
+    double2 *Tc = reinterpret_cast<double2 *>(T);
+    for (int t = blockIdx.x * kT + threadIdx.x; t < rows * m; t += gridDim.x * kT) {
+        const int r = t % rows, c = t / rows;
+        Tc[(int64_t)c * ldt + r] = Sc[(int64_t)order[c] * lds + r];
+    }
+}
+
 // Precision conversion of a blocked block vector (count complex entries).
 __global__ __launch_bounds__(kT) void convert_kernel(const void *src, int prec_src, void *dst,
                                                      int prec_dst, int64_t count) {
@@ -541,14 +552,15 @@ __device__ inline uint64_t splitmix64(uint64_t z) {
 // k = splitmix64(splitmix64(seed) ^ (col0 + c - c_begin)).
 __global__ __launch_bounds__(kT) void random_phase_kernel(void *X, int prec, int64_t n, int nb,
                                                           int c_begin, int c_end, uint64_t seed,
-                                                          uint64_t col0) {
+                                                          uint64_t col0, const int32_t *perm) {
     const uint64_t base = splitmix64(seed);
     const int64_t cols = c_end - c_begin;
     for (int64_t t = blockIdx.x * (int64_t)kT + threadIdx.x; t < n * cols;
          t += (int64_t)gridDim.x * kT) {
         const int64_t cc = t / n, i = t % n;
         const uint64_t kj = splitmix64(base ^ (col0 + (uint64_t)cc));
-        const double u = (double)(splitmix64(kj ^ (uint64_t)i) >> 11) * 0x1.0p-53;
+        const uint64_t row = perm ? (uint64_t)perm[i] : (uint64_t)i;  // the row's original index
+        const double u = (double)(splitmix64(kj ^ row) >> 11) * 0x1.0p-53;
         double sn, cs;
         sincospi(2.0 * u, &sn, &cs);
         store_c(X, prec, blocked_index(n, nb, i, c_begin + static_cast<int>(cc)), double2{cs, sn});
@@ -607,12 +619,12 @@ __global__ __launch_bounds__(kT) void scale_columns_kernel(void *Z, int prec, in
 
 }  // namespace
 
-int launch_gram(const void *A, const void *B, int prec, int64_t n, int nb, int m1, int m2,
-                double *part, int nsplit, double *S, int ld, hipStream_t s) {
+int launch_gram(const void *A, int prec_a, int nb_a, const void *B, int prec_b, int nb_b, int64_t n,
+                int m1, int m2, double *part, int nsplit, double *S, int ld, hipStream_t s) {
     const int ta = (m1 + kGT - 1) / kGT, tb = (m2 + kGT - 1) / kGT;
     const int64_t rps = ((n + nsplit - 1) / nsplit + kGK - 1) / kGK * kGK;
-    hipLaunchKernelGGL(gram_kernel, dim3(ta * tb, nsplit), dim3(kT), 0, s, A, B, prec, n, nb, m1, m2,
-                       ta, tb, rps, part);
+    hipLaunchKernelGGL(gram_kernel, dim3(ta * tb, nsplit), dim3(kT), 0, s, A, prec_a, nb_a, B, prec_b, nb_b,
+                       n, m1, m2, ta, tb, rps, part);
     CHEBFD_HIP(hipGetLastError());
     const int64_t total = (int64_t)ta * tb * kGT * kGT;
     int G = static_cast<int>((total + kT - 1) / kT);
@@ -684,6 +696,14 @@ int launch_resid(const void *HZ, const void *Z, int prec, int64_t n, int nb, con
     return CHEBFD_OK;
 }
 
+int launch_permute_columns(int rows, int m, const double *S, int lds, const int *order, double *T,
+                           int ldt, hipStream_t s) {
+    hipLaunchKernelGGL(permute_columns_kernel, dim3(grid_cap((int64_t)rows * m)), dim3(kT), 0, s, rows, m, S,
+                       lds, order, T, ldt);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
 int launch_convert(const void *src, int prec_src, void *dst, int prec_dst, int64_t count,
                    hipStream_t s) {
     hipLaunchKernelGGL(convert_kernel, dim3(grid_cap(count, 65536)), dim3(kT), 0, s, src, prec_src, dst,
@@ -693,10 +713,10 @@ int launch_convert(const void *src, int prec_src, void *dst, int prec_dst, int64
 }
 
 int launch_random_phase(void *X, int prec, int64_t n, int nb, int c_begin, int c_end, uint64_t seed,
-                        uint64_t col0, hipStream_t s) {
+                        uint64_t col0, const int32_t *perm, hipStream_t s) {
     if (c_end <= c_begin) return CHEBFD_OK;
     hipLaunchKernelGGL(random_phase_kernel, dim3(grid_cap(n * (c_end - c_begin), 65536)), dim3(kT), 0, s,
-                       X, prec, n, nb, c_begin, c_end, seed, col0);
+                       X, prec, n, nb, c_begin, c_end, seed, col0, perm);
     CHEBFD_HIP(hipGetLastError());
     return CHEBFD_OK;
 }

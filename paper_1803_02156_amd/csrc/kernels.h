@@ -67,8 +67,8 @@ int launch_reduce(int nb, const StepArgs &a, hipStream_t s);
 int step_grid(int prec, int nb, int64_t npass, int num_cus);
 
 // dense kernels (dense.hip)
-int launch_gram(const void *A, const void *B, int prec, int64_t n, int nb, int m1, int m2,
-                double *part, int nsplit, double *S, int ld, hipStream_t s);
+int launch_gram(const void *A, int prec_a, int nb_a, const void *B, int prec_b, int nb_b, int64_t n,
+                int m1, int m2, double *part, int nsplit, double *S, int ld, hipStream_t s);
 size_t gram_part_bytes(int m1, int m2, int nsplit);
 int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm, void *Z, int prec_z,
                   int nb_z, int64_t n, int m1, int m2, hipStream_t s);
@@ -85,7 +85,9 @@ int launch_resid(const void *HZ, const void *Z, int prec, int64_t n, int nb, con
 int launch_convert(const void *src, int prec_src, void *dst, int prec_dst, int64_t count,
                    hipStream_t s);
 int launch_random_phase(void *X, int prec, int64_t n, int nb, int c_begin, int c_end, uint64_t seed,
-                        uint64_t col0, hipStream_t s);
+                        uint64_t col0, const int32_t *perm, hipStream_t s);
+int launch_permute_columns(int rows, int m, const double *S, int lds, const int *order, double *T,
+                           int ldt, hipStream_t s);
 int launch_fix_phases(void *Z, int prec, int64_t n, int nb, int m, double *phase, hipStream_t s);
 
 // layout / misc kernels (layout.hip)

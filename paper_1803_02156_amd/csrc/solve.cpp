@@ -1,0 +1,445 @@
+// ChebFD outer loop on the device: filter (Alg. 1 / Alg. 2), SVQB
+// orthonormalisation (twice, rank revealing), Rayleigh-Ritz on the kept
+// directions, FP64 residuals, restart.  The paper describes the filter and names
+// the orthogonalisation before the restart (Sect. 2); the restart and
+// convergence rules used here are stated in include/chebfd.h.
+//
+// Host work per iteration: deciding how many SVQB directions to keep (needs the
+// Gram eigenvalues), the convergence test (needs the Ritz values and
+// residuals), and on the first iteration the eigenvalue-count estimate from the
+// moments.  These are the only device -> host copies; everything else is
+// enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace chebfd {
+namespace {
+
+size_t al(size_t v) { return round_up(v, 256); }
+
+int gram_splits(int64_t n) {
+    return static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, n / 256)));
+}
+
+struct SolveLayout {
+    size_t x, q, u, w, z64, t64, b64;
+    size_t S, V, G, T, wv, d, theta, rr, phase, order;
+    size_t eta, nu, fwork, gpart, rpart, jwork;
+    size_t fwork_bytes, gpart_bytes, rpart_bytes, jwork_bytes, total;
+    int rgrid;
+};
+
+int solve_layout(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_params *p,
+                 SolveLayout *L) {
+    const size_t n = H->n, ns = p->n_s, nb = p->n_b, sw = vec_elem_bytes(p->prec);
+    size_t f1 = 0, f2 = 0;
+    int rc = chebfd_filter_query(H, p->n_b, &f1);
+    if (rc) return rc;
+    if ((rc = chebfd_filter_query(H64, p->n_b, &f2))) return rc;
+    L->fwork_bytes = std::max(f1, f2);
+    L->gpart_bytes = gram_part_bytes(p->n_s, p->n_s, gram_splits(H->n));
+    L->rgrid = resid_grid(H->n);
+    L->rpart_bytes = (size_t)2 * nb * L->rgrid * 8;
+    if ((rc = chebfd_heev_query(p->n_s, &L->jwork_bytes))) return rc;
+    size_t at = 0;
+    auto take = [&](size_t bytes) { size_t h = at; at += al(bytes); return h; };
+    L->x = take(n * ns * sw);
+    L->q = take(n * ns * sw);
+    L->u = take(n * nb * sw);
+    L->w = take(n * nb * sw);
+    L->z64 = take(n * nb * 16);
+    L->t64 = take(n * nb * 16);
+    L->b64 = take(n * nb * 16);
+    L->S = take(ns * ns * 16);
+    L->V = take(ns * ns * 16);
+    L->G = take(ns * ns * 16);
+    L->T = take(ns * ns * 16);
+    L->wv = take(ns * 8);
+    L->d = take(ns * 8);
+    L->theta = take(ns * 8);
+    L->rr = take(2 * nb * 8);
+    L->phase = take(2 * ns * 8);
+    L->order = take(ns * 4);
+    L->eta = take((size_t)(p->n_p + 1) * ns * 16);
+    L->nu = take((size_t)(p->n_p + 1) * ns * 8);
+    L->fwork = take(L->fwork_bytes);
+    L->gpart = take(L->gpart_bytes);
+    L->rpart = take(L->rpart_bytes);
+    L->jwork = take(L->jwork_bytes);
+    L->total = at;
+    return CHEBFD_OK;
+}
+
+int check_params(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_params *p) {
+    CHEBFD_REQUIRE(H && H64 && p, "NULL argument");
+    CHEBFD_REQUIRE(H->n >= 1 && H->val && H64->val, "matrix handle not built");
+    CHEBFD_REQUIRE(H64->prec == CHEBFD_PREC_FP64, "H64 must hold FP64 values");
+    CHEBFD_REQUIRE(H->prec == p->prec, "p->prec %d differs from the matrix's %d", p->prec, H->prec);
+    CHEBFD_REQUIRE(H64->n == H->n && H64->C == H->C && H64->sigma == H->sigma &&
+                       H64->identity_perm == H->identity_perm,
+                   "H and H64 must be built from the same matrix with the same C and sigma");
+    CHEBFD_REQUIRE(p->n_b >= 1 && p->n_b <= 128 && (p->n_b & (p->n_b - 1)) == 0,
+                   "n_b = %d must be a power of two in [1, 128]", p->n_b);
+    CHEBFD_REQUIRE(p->n_s >= p->n_b && p->n_s % p->n_b == 0 && p->n_s <= 512,
+                   "n_s = %d must be a multiple of n_b and at most 512", p->n_s);
+    CHEBFD_REQUIRE(p->n_p >= 2, "n_p = %d < 2", p->n_p);
+    CHEBFD_REQUIRE(p->max_iter >= 1, "max_iter < 1");
+    CHEBFD_REQUIRE(std::isfinite(p->lam_L) && std::isfinite(p->lam_R) && p->lam_L < p->lam_R,
+                   "search interval invalid");
+    CHEBFD_REQUIRE(p->tol > 0.0, "tol must be positive");
+    return CHEBFD_OK;
+}
+
+double tau_for(int prec) {
+    const double eps = 0x1.0p-53, es = prec == CHEBFD_PREC_FP64 ? 0x1.0p-53 : 0x1.0p-24;
+    return std::max(100.0 * eps, (10.0 * es) * (10.0 * es));
+}
+
+struct Timer {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Timer() {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+}  // namespace
+}  // namespace chebfd
+
+using namespace chebfd;
+
+extern "C" {
+
+int chebfd_gram_query(int64_t n, int32_t m1, int32_t m2, size_t *work_bytes) {
+    clear_error();
+    CHEBFD_REQUIRE(n >= 1 && m1 >= 1 && m2 >= 1 && work_bytes, "invalid Gram sizes");
+    *work_bytes = gram_part_bytes(m1, m2, gram_splits(n));
+    return CHEBFD_OK;
+}
+
+int chebfd_gram(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec, const void *d_a,
+                const void *d_b, double *d_s, int32_t ld, void *d_work, size_t work_bytes,
+                void *stream) {
+    clear_error();
+    CHEBFD_REQUIRE(n >= 1 && m1 >= 1 && m2 >= 1 && ld >= m1, "invalid Gram sizes");
+    CHEBFD_REQUIRE(n_b >= 1 && n_b <= 128 && (n_b & (n_b - 1)) == 0, "n_b = %d invalid", n_b);
+    CHEBFD_REQUIRE(prec == CHEBFD_PREC_FP64 || prec == CHEBFD_PREC_MIXED, "prec invalid");
+    CHEBFD_REQUIRE(d_a && d_b && d_s && d_work, "NULL buffer");
+    size_t need;
+    int rc = chebfd_gram_query(n, m1, m2, &need);
+    if (rc) return rc;
+    if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "Gram workspace %zu < %zu", work_bytes, need);
+    return launch_gram(d_a, prec, n_b, d_b, prec, n_b, n, m1, m2, static_cast<double *>(d_work),
+                       gram_splits(n), d_s, ld, static_cast<hipStream_t>(stream));
+}
+
+int chebfd_update(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec_a, const void *d_a,
+                  const double *d_m, int32_t ldm, int32_t prec_z, void *d_z, void *stream) {
+    clear_error();
+    CHEBFD_REQUIRE(n >= 1 && m1 >= 1 && m2 >= 1 && ldm >= m1, "invalid update sizes");
+    CHEBFD_REQUIRE(n_b >= 1 && n_b <= 128 && (n_b & (n_b - 1)) == 0, "n_b = %d invalid", n_b);
+    CHEBFD_REQUIRE(d_a && d_m && d_z, "NULL buffer");
+    CHEBFD_REQUIRE(!overlap(d_a, vec_elem_bytes(prec_a) * (size_t)n * ((m1 + n_b - 1) / n_b * n_b), d_z,
+                            vec_elem_bytes(prec_z) * (size_t)n * ((m2 + n_b - 1) / n_b * n_b)),
+                   "A and Z overlap");
+    return launch_update(d_a, prec_a, n_b, d_m, ldm, d_z, prec_z, n_b, n, m1, m2,
+                         static_cast<hipStream_t>(stream));
+}
+
+int chebfd_heev_query(int32_t m, size_t *work_bytes) {
+    clear_error();
+    CHEBFD_REQUIRE(m >= 1 && m <= 512 && work_bytes, "eigensolver size %d not in [1, 512]", m);
+    *work_bytes = al(2 * (size_t)m * 8 + 64) + 256;
+    return CHEBFD_OK;
+}
+
+int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, double *d_w,
+                void *d_work, size_t work_bytes, void *stream, int32_t *h_sweeps) {
+    clear_error();
+    size_t need;
+    int rc = chebfd_heev_query(m, &need);
+    if (rc) return rc;
+    CHEBFD_REQUIRE(d_a && d_v && d_w && d_work && lda >= m && ldv >= m, "invalid eigensolver arguments");
+    if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "eigensolver workspace %zu < %zu", work_bytes, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int *info = static_cast<int *>(d_work);
+    double *scratch = reinterpret_cast<double *>(static_cast<char *>(d_work) + 256);
+    if ((rc = launch_jacobi(m, d_a, lda, d_v, ldv, d_w, 40, 0x1.0p-52, info, scratch, s))) return rc;
+    int h[2];
+    CHEBFD_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, s));
+    CHEBFD_HIP(hipStreamSynchronize(s));
+    if (h_sweeps) *h_sweeps = h[0];
+    if (h[1]) CHEBFD_FAIL(CHEBFD_ENUMERIC, "Jacobi eigensolver did not converge in %d sweeps", h[0]);
+    return CHEBFD_OK;
+}
+
+int chebfd_solve_query(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_params *p,
+                       size_t *work_bytes) {
+    clear_error();
+    int rc = check_params(H, H64, p);
+    if (rc) return rc;
+    CHEBFD_REQUIRE(work_bytes != nullptr, "work_bytes is NULL");
+    SolveLayout L;
+    if ((rc = solve_layout(H, H64, p, &L))) return rc;
+    *work_bytes = L.total;
+    return CHEBFD_OK;
+}
+
+int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_params *p,
+                 const void *d_x0, void *d_work, size_t work_bytes, void *stream, int32_t *n_found,
+                 double *h_theta, void *d_Z, double *h_resid, chebfd_stats *st) {
+    clear_error();
+    int rc = check_params(H, H64, p);
+    if (rc) return rc;
+    CHEBFD_REQUIRE(d_work && aligned(d_work, 256), "d_work must be non-NULL and 256-byte aligned");
+    CHEBFD_REQUIRE(n_found && h_theta && h_resid, "output pointer is NULL");
+    SolveLayout L;
+    if ((rc = solve_layout(H, H64, p, &L))) return rc;
+    if (work_bytes < L.total) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "solve workspace %zu < %zu", work_bytes, L.total);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(d_work);
+    auto D = [&](size_t off) { return static_cast<void *>(base + off); };
+    auto DD = [&](size_t off) { return reinterpret_cast<double *>(base + off); };
+    const int64_t n = H->n;
+    const int ns = p->n_s, nb = p->n_b, prec = p->prec;
+    const size_t sw = vec_elem_bytes(prec);
+    const int32_t *perm = H->identity_perm ? nullptr : H->perm;
+
+    // spectral scaling and filter coefficients
+    double lo = p->spec_lo, hi = p->spec_hi;
+    if (!std::isfinite(lo) || !std::isfinite(hi)) {
+        size_t bq;
+        if ((rc = chebfd_bounds_query(H64, &bq))) return rc;
+        if (bq > L.fwork_bytes) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "bounds workspace");
+        if ((rc = chebfd_bounds(H64, D(L.fwork), L.fwork_bytes, stream, &lo, &hi))) return rc;
+    }
+    double alpha, beta;
+    std::vector<double> gamma(p->n_p + 1), gamma2(2 * p->n_p);
+    if ((rc = chebfd_coefficients(lo, hi, p->lam_L, p->lam_R, p->n_p, &alpha, &beta, gamma.data()))) return rc;
+    if ((rc = chebfd_coefficients(lo, hi, p->lam_L, p->lam_R, 2 * p->n_p - 1, &alpha, &beta, gamma2.data())))
+        return rc;
+
+    // start block
+    if (d_x0) {
+        if ((rc = chebfd_pack(H, ns, nb, prec, d_x0, D(L.x), stream))) return rc;
+    } else {
+        if ((rc = launch_random_phase(D(L.x), prec, n, nb, 0, ns, p->seed, 0, perm, s))) return rc;
+    }
+
+    Timer ev[5];
+    for (auto &t : ev)
+        for (auto &e : t.e) CHEBFD_HIP(hipEventCreate(&e));
+    double t_phase[4] = {0, 0, 0, 0};
+    const double tau = tau_for(prec);
+    std::vector<double> hw(ns), hth(ns), hrr(2 * nb), hres(ns), hnrm(ns);
+    std::vector<double> heta, hnu;
+    double count_est = 0.0;
+    int status = CHEBFD_NOT_CONVERGED, it = 0, prev = -1, k2 = 0;
+    double fbytes = 0.0;
+    void *X = D(L.x), *Q = D(L.q);
+
+    // one SVQB step: A (m columns) -> B (k kept columns); returns k
+    auto svqb = [&](void *A, int m, void *B, int *k) -> int {
+        int r;
+        if ((r = launch_gram(A, prec, nb, A, prec, nb, n, m, m, DD(L.gpart), gram_splits(n), DD(L.S), ns, s)))
+            return r;
+        if ((r = launch_svqb_scale(m, DD(L.S), ns, DD(L.d), s))) return r;
+        if ((r = chebfd_heev(m, DD(L.S), ns, DD(L.V), ns, DD(L.wv), D(L.jwork), L.jwork_bytes, stream, nullptr)))
+            return r;
+        CHEBFD_HIP(hipMemcpyAsync(hw.data(), DD(L.wv), sizeof(double) * m, hipMemcpyDeviceToHost, s));
+        CHEBFD_HIP(hipStreamSynchronize(s));
+        const double wmax = hw[m - 1];
+        if (!(wmax > 0.0) || !std::isfinite(wmax)) CHEBFD_FAIL(CHEBFD_ENUMERIC, "SVQB: non-positive Gram matrix");
+        int kk = 0;
+        for (int i = 0; i < m; ++i) kk += hw[i] > tau * wmax ? 1 : 0;
+        if ((r = launch_svqb_transform(m, kk, m - kk, DD(L.d), DD(L.V), ns, DD(L.wv), DD(L.T), ns, s))) return r;
+        if ((r = launch_update(A, prec, nb, DD(L.T), ns, B, prec, nb, n, m, kk, s))) return r;
+        *k = kk;
+        return CHEBFD_OK;
+    };
+
+    for (it = 1; it <= p->max_iter; ++it) {
+        // --- filter (Alg. 2 over blocks, Alg. 1 per block) ---
+        CHEBFD_HIP(hipEventRecord(ev[0].e[0], s));
+        double *d_eta = it == 1 ? DD(L.eta) : nullptr, *d_nu = it == 1 ? DD(L.nu) : nullptr;
+        if ((rc = chebfd_filter(H, alpha, beta, gamma.data(), p->n_p, ns, nb, prec, X, D(L.u), D(L.w), d_eta,
+                                d_nu, D(L.fwork), L.fwork_bytes, stream)))
+            return rc;
+        CHEBFD_HIP(hipEventRecord(ev[0].e[1], s));
+        fbytes += (double)(ns / nb) * ((double)(p->n_p - 2) * (double)(H->nnz * (sw + 4) + 5 * n * nb * sw) +
+                                       2.0 * (double)(H->nnz * (sw + 4)) + 6.0 * n * nb * sw);
+        if (it == 1) {
+            // moments -> eigenvalue count estimate (trace of the damped window polynomial)
+            heta.resize((size_t)2 * (p->n_p + 1) * ns);
+            hnu.resize((size_t)(p->n_p + 1) * ns);
+            CHEBFD_HIP(hipMemcpyAsync(heta.data(), DD(L.eta), sizeof(double) * heta.size(), hipMemcpyDeviceToHost, s));
+            CHEBFD_HIP(hipMemcpyAsync(hnu.data(), DD(L.nu), sizeof(double) * hnu.size(), hipMemcpyDeviceToHost, s));
+            CHEBFD_HIP(hipStreamSynchronize(s));
+            std::vector<double> se(p->n_p + 1, 0.0), sn(p->n_p + 1, 0.0);
+            for (int q = 1; q <= p->n_p; ++q)
+                for (int j = 0; j < ns; ++j) {
+                    se[q] += heta[2 * ((size_t)q * ns + j)];
+                    sn[q] += hnu[(size_t)q * ns + j];
+                }
+            const double mu0 = sn[1], mu1 = se[1];
+            double acc = gamma2[0] * mu0 + gamma2[1] * mu1;
+            for (int k = 1; k < p->n_p; ++k)
+                acc += gamma2[2 * k] * (2.0 * sn[k + 1] - mu0) + gamma2[2 * k + 1] * (2.0 * se[k + 1] - mu1);
+            count_est = acc / ns;   // n * sum g c mu~ with mu~ = mu / (n R)
+        }
+
+        // --- SVQB twice ---
+        CHEBFD_HIP(hipEventRecord(ev[1].e[0], s));
+        int k1 = 0;
+        if ((rc = svqb(X, ns, Q, &k1))) return rc;
+        if ((rc = svqb(Q, k1, X, &k2))) return rc;
+        CHEBFD_HIP(hipEventRecord(ev[1].e[1], s));
+
+        // --- Rayleigh-Ritz on the k2 kept directions (FP64 products) ---
+        CHEBFD_HIP(hipEventRecord(ev[2].e[0], s));
+        const int kb = (k2 + nb - 1) / nb;
+        for (int b = 0; b < kb; ++b) {
+            const void *Xb = static_cast<const char *>(X) + (size_t)b * n * nb * sw;
+            const void *X64 = Xb;
+            if (prec != CHEBFD_PREC_FP64) {
+                if ((rc = launch_convert(Xb, prec, D(L.b64), CHEBFD_PREC_FP64, n * nb, s))) return rc;
+                X64 = D(L.b64);
+            }
+            if ((rc = chebfd_spmmv(H64, 1.0, 0.0, nb, CHEBFD_PREC_FP64, X64, D(L.t64), D(L.fwork), L.fwork_bytes,
+                                   stream)))
+                return rc;
+            const int cols = std::min(nb, k2 - b * nb);
+            if ((rc = launch_gram(X, prec, nb, D(L.t64), CHEBFD_PREC_FP64, nb, n, k2, cols, DD(L.gpart),
+                                  gram_splits(n), DD(L.G) + 2 * (size_t)b * nb * ns, ns, s)))
+                return rc;
+        }
+        if ((rc = launch_hermitise(k2, DD(L.G), ns, s))) return rc;
+        if ((rc = chebfd_heev(k2, DD(L.G), ns, DD(L.S), ns, DD(L.theta), D(L.jwork), L.jwork_bytes, stream,
+                              nullptr)))
+            return rc;
+        CHEBFD_HIP(hipEventRecord(ev[2].e[1], s));
+
+        // --- residuals ||H z - theta z|| / ||z|| with z = X S in FP64 ---
+        CHEBFD_HIP(hipEventRecord(ev[3].e[0], s));
+        for (int b = 0; b < kb; ++b) {
+            const int cols = std::min(nb, k2 - b * nb);
+            if ((rc = launch_update(X, prec, nb, DD(L.S) + 2 * (size_t)b * nb * ns, ns, D(L.z64), CHEBFD_PREC_FP64,
+                                    nb, n, k2, cols, s)))
+                return rc;
+            if ((rc = chebfd_spmmv(H64, 1.0, 0.0, nb, CHEBFD_PREC_FP64, D(L.z64), D(L.t64), D(L.fwork),
+                                   L.fwork_bytes, stream)))
+                return rc;
+            if ((rc = launch_resid(D(L.t64), D(L.z64), CHEBFD_PREC_FP64, n, nb, DD(L.theta) + (size_t)b * nb,
+                                   DD(L.rpart), L.rgrid, DD(L.rr), s)))
+                return rc;
+            CHEBFD_HIP(hipMemcpyAsync(hrr.data(), DD(L.rr), sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s));
+            CHEBFD_HIP(hipStreamSynchronize(s));
+            for (int c = 0; c < cols; ++c) {
+                hres[b * nb + c] = std::sqrt(hrr[2 * c]);
+                hnrm[b * nb + c] = std::sqrt(hrr[2 * c + 1]);
+            }
+        }
+        CHEBFD_HIP(hipMemcpyAsync(hth.data(), DD(L.theta), sizeof(double) * k2, hipMemcpyDeviceToHost, s));
+        CHEBFD_HIP(hipEventRecord(ev[3].e[1], s));
+        CHEBFD_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < 4; ++q) {
+            float ms = 0.0f;
+            CHEBFD_HIP(hipEventElapsedTime(&ms, ev[q].e[0], ev[q].e[1]));
+            t_phase[q] += ms * 1e-3;
+        }
+        for (int c = 0; c < k2; ++c) {
+            hres[c] = hnrm[c] > 0.0 ? hres[c] / hnrm[c] : INFINITY;
+            if (!std::isfinite(hth[c])) CHEBFD_FAIL(CHEBFD_ENUMERIC, "non-finite Ritz value");
+        }
+
+        // --- convergence test ---
+        int inwin = 0, conv = 0;
+        bool all_ok = true;
+        for (int c = 0; c < k2; ++c) {
+            if (hth[c] < p->lam_L || hth[c] > p->lam_R) continue;
+            ++inwin;
+            const bool cv = hres[c] <= p->tol;
+            const bool spur = hres[c] > 0.5 * (p->lam_R - p->lam_L);
+            conv += cv ? 1 : 0;
+            all_ok = all_ok && (cv || spur);
+        }
+        if (inwin > 0.75 * ns) {
+            status = CHEBFD_SUBSPACE_SMALL;
+            break;
+        }
+        if (conv == prev && all_ok) {
+            status = CHEBFD_OK;
+            break;
+        }
+        prev = conv;
+        if (it == p->max_iter) break;
+
+        // --- restart: Ritz vectors, then fresh random phases for dropped directions ---
+        if ((rc = launch_update(X, prec, nb, DD(L.S), ns, Q, prec, nb, n, k2, k2, s))) return rc;
+        if ((rc = launch_random_phase(Q, prec, n, nb, k2, ns, p->seed, (uint64_t)it * ns, perm, s))) return rc;
+        std::swap(X, Q);
+    }
+    if (it > p->max_iter) it = p->max_iter;
+
+    // output order: converged pairs inside the interval first, then the rest
+    std::vector<int> order;
+    for (int c = 0; c < k2; ++c)
+        if (hth[c] >= p->lam_L && hth[c] <= p->lam_R && hres[c] <= p->tol) order.push_back(c);
+    const int nf = static_cast<int>(order.size());
+    for (int c = 0; c < k2; ++c)
+        if (!(hth[c] >= p->lam_L && hth[c] <= p->lam_R && hres[c] <= p->tol)) order.push_back(c);
+    for (int c = 0; c < ns; ++c) {
+        h_theta[c] = c < k2 ? hth[order[c]] : NAN;
+        h_resid[c] = c < k2 ? hres[order[c]] : NAN;
+    }
+    *n_found = nf;
+    if (d_Z) {
+        CHEBFD_HIP(hipMemcpyAsync(D(L.order), order.data(), sizeof(int) * k2, hipMemcpyHostToDevice, s));
+        if ((rc = launch_permute_columns(k2, k2, DD(L.S), ns, static_cast<const int *>(D(L.order)), DD(L.T), ns, s)))
+            return rc;
+        CHEBFD_HIP(hipMemsetAsync(d_Z, 0, sizeof(double) * 2 * (size_t)n * ns, s));
+        const int kb = (k2 + nb - 1) / nb;
+        for (int b = 0; b < kb; ++b) {
+            const int cols = std::min(nb, k2 - b * nb);
+            if ((rc = launch_update(X, prec, nb, DD(L.T) + 2 * (size_t)b * nb * ns, ns, D(L.z64), CHEBFD_PREC_FP64,
+                                    nb, n, k2, cols, s)))
+                return rc;
+            if ((rc = launch_fix_phases(D(L.z64), CHEBFD_PREC_FP64, n, nb, cols, DD(L.phase), s))) return rc;
+            if ((rc = launch_pack(perm, n, nb, nb, CHEBFD_PREC_FP64, D(L.z64),
+                                  static_cast<char *>(d_Z) + (size_t)b * nb * n * 16, true, s)))
+                return rc;
+        }
+        if (k2 % nb) {
+            // the last block's columns past k2 received the update's zeros; re-zero to be explicit
+            const int b = k2 / nb;
+            const size_t c0 = (size_t)k2;
+            CHEBFD_HIP(hipMemsetAsync(static_cast<char *>(d_Z) + c0 * n * 16, 0, ((size_t)(b + 1) * nb - c0) * n * 16, s));
+        }
+        CHEBFD_HIP(hipStreamSynchronize(s));
+    }
+    if (st) {
+        st->iterations = it;
+        st->n_found = nf;
+        st->n_kept = k2;
+        st->status = status;
+        st->count_est = count_est;
+        st->t_filter = t_phase[0];
+        st->t_orth = t_phase[1];
+        st->t_rr = t_phase[2];
+        st->t_resid = t_phase[3];
+        st->t_total = t_phase[0] + t_phase[1] + t_phase[2] + t_phase[3];
+        st->filter_bytes = fbytes;
+    }
+    return status;
+}
+
+}  // extern "C"
