@@ -279,6 +279,77 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
                  double *h_theta, void *d_Z, double *h_resid, chebfd_stats *st);
 
 /*
+ * Parameter choice (n_p, n_s) for chebfd_solve.  The paper fixes n_p and n_s
+ * by hand (Sect. 2: n_s above the number of wanted eigenpairs; Sect. 5:
+ * n_p around 10^3) and points to the KPM moments of the filter's dot products
+ * as the cheap view of the spectrum (Sect. 2).  Two predictors use them:
+ *  - a heuristic: n_s = max(n_b, round_up_{n_b}(2 n_hat)),
+ *    n_p = clamp(round(kappa / delta), 50, 20000) with delta = (b~ - a~) / 2
+ *    the half width of the scaled interval and n_hat the eigenvalue count
+ *    estimate from the moments;
+ *  - a small MLP (below) on the moment features, whose two outputs are the
+ *    standardised log n_p and log n_s.
+ */
+#define CHEBFD_FEATURE_R        16   /* random-phase vectors of the feature moments */
+#define CHEBFD_FEATURE_MOMENTS  256  /* moments mu~_0 .. mu~_255 (128 Chebyshev steps) */
+#define CHEBFD_MLP_IN     258        /* 256 moments + [a~, b~] */
+#define CHEBFD_MLP_HIDDEN 128
+#define CHEBFD_MLP_OUT    2
+#define CHEBFD_MLP_PARAMS 49922      /* 128*258 + 128 + 128*128 + 128 + 2*128 + 2 */
+#define CHEBFD_NP_MIN     50
+#define CHEBFD_NP_MAX     20000
+
+typedef struct chebfd_predictor {
+    double kappa;           /* heuristic: n_p = kappa / delta */
+    double t_mean[2];       /* MLP output de-standardisation: log n_p, log n_s */
+    double t_std[2];
+} chebfd_predictor;
+
+/*
+ * Features of (H, [lam_L, lam_R]): Gershgorin scaling (alpha, beta), the
+ * CHEBFD_FEATURE_MOMENTS averaged moments of chebfd_kpm_moments with
+ * CHEBFD_FEATURE_R vectors from `seed`, then a~ = alpha lam_L + beta and
+ * b~ = alpha lam_R + beta: h_features[258] (FP32, host).  *count_est: the
+ * eigenvalue count estimate n sum_m g_m c_m mu~_m over the same moments (window
+ * coefficients of [a~, b~] and Jackson damping for 256 terms).  Synchronises.
+ * CHEBFD_EINTERVAL unless -1 < a~ < b~ < 1.
+ */
+int chebfd_features_query(const chebfd_matrix *H, size_t *work_bytes);
+int chebfd_features(const chebfd_matrix *H, double lam_L, double lam_R, uint64_t seed, float *h_features,
+                    double *count_est, double *alpha, double *beta, void *d_work, size_t work_bytes,
+                    void *stream);
+
+/*
+ * (n_p, n_s) from the scaled interval [a, b], the count estimate and either the
+ * MLP's two outputs (h_mlp_out, host, standardised log n_p and log n_s) or,
+ * with h_mlp_out NULL, the heuristic.  Both are clamped: n_p to
+ * [CHEBFD_NP_MIN, CHEBFD_NP_MAX]; n_s to a multiple of n_b that is at least
+ * max(n_b, 1.2 n_hat) and at most 512.  Host only, no device work.
+ */
+int chebfd_choose_params(double a, double b, double count_est, int32_t n_b, const float *h_mlp_out,
+                         const chebfd_predictor *pr, int32_t *n_p, int32_t *n_s);
+
+/*
+ * The predictor network (FP32, device): x (258) -> relu(W1 x + b1) (128)
+ * -> relu(W2 h1 + b2) (128) -> y = W3 h2 + b3 (2).  d_params: the flat
+ * CHEBFD_MLP_PARAMS vector W1, b1, W2, b2, W3, b3, weight matrices row-major
+ * with the output index slowest (caller-owned).  Batches are row-major:
+ * d_x batch x 258, d_y / d_t batch x 2.  d_work: chebfd_mlp_query bytes,
+ * 256-byte aligned.  Results are bit-reproducible (fixed summation orders).
+ *  forward: d_y = network(d_x).
+ *  grad:    d_loss[0] = sum ||y - t||^2 / (2 batch), d_grad = d loss / d params.
+ *  adam:    one Adam step (Kingma and Ba; bias-corrected, step counts from 1)
+ *           on params with moment buffers d_m, d_v (zero before step 1).
+ */
+int chebfd_mlp_query(int32_t batch, int32_t *n_params, size_t *work_bytes);
+int chebfd_mlp_forward(const float *d_params, int32_t batch, const float *d_x, float *d_y, void *d_work,
+                       size_t work_bytes, void *stream);
+int chebfd_mlp_grad(const float *d_params, int32_t batch, const float *d_x, const float *d_t, float *d_loss,
+                    float *d_grad, void *d_work, size_t work_bytes, void *stream);
+int chebfd_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t step, float lr,
+                    float beta1, float beta2, float eps, void *stream);
+
+/*
  * HBM bandwidth probe (the STREAM analogue of Sect. 1.2, Table 2): copy
  * (b = a) or triad (a = b + s c) over `count` doubles.  kind 0 = copy,
  * kind 1 = triad.

@@ -13,6 +13,7 @@ small dense steps use numpy's LAPACK routines as library primitives.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -22,7 +23,7 @@ from . import build as _build
 __all__ = [
     "load_library", "gershgorin_bounds", "scale_factors", "window_coefficients",
     "jackson_damping", "filter_coefficients", "spmmv", "chebyshev_filter",
-    "kpm_moments", "count_estimate", "svqb", "rayleigh_ritz", "residual_norms",
+    "kpm_moments", "count_estimate", "choose_params", "svqb", "rayleigh_ritz", "residual_norms",
     "fix_phases", "chebfd_solve", "SolveResult",
 ]
 
@@ -203,6 +204,31 @@ def count_estimate(mu: np.ndarray, n: int, a: float, b: float) -> float:
     mut = np.real(np.sum(mu, axis=1)) / (n * mu.shape[1])
     coef = jackson_damping(M - 1) * window_coefficients(a, b, M - 1)
     return float(n * np.dot(coef, mut))
+
+
+def choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, kappa: float = 1.0,
+                  t_mean=(0.0, 0.0), t_std=(1.0, 1.0), np_min=50, np_max=20000, ns_max=512):
+    """(n_p, n_s) for the scaled interval [a, b] and a count estimate.
+
+    The paper picks n_s a bit above the number of wanted eigenpairs (Sect. 2)
+    and n_p around 10^3 for its problems (Sect. 5); it gives no rule.  The
+    reading used here: the filter's resolution scales like 1 / n_p in the
+    scaled variable, so n_p = kappa / delta with delta = (b - a) / 2, and
+    n_s = 2 n_hat rounded up to a block.  A network may instead give
+    standardised (log n_p, log n_s); n_s then stays at least 1.2 n_hat.
+    Clamped: n_p in [np_min, np_max], n_s a multiple of n_b in [n_b, ns_max].
+    """
+    nhat = max(count_est, 0.0)
+    if mlp_out is None:
+        np_real = kappa / ((b - a) / 2.0)
+        ns_real = 2.0 * nhat
+    else:
+        np_real = math.exp(min(30.0, float(mlp_out[0]) * t_std[0] + t_mean[0]))
+        ns_real = max(math.exp(min(30.0, float(mlp_out[1]) * t_std[1] + t_mean[1])), 1.2 * nhat)
+    n_p = int(min(np_max, max(np_min, math.floor(np_real + 0.5))))   # halves round up
+    n_s = int(math.ceil(ns_real / n_b) * n_b)
+    n_s = min(max(n_s, n_b), max(n_b, ns_max // n_b * n_b))
+    return n_p, n_s
 
 
 # ---------------------------------------------------------------------------

@@ -10,6 +10,9 @@ LIB_PATH = os.path.join(HERE, "libchebfd.so")
 OK, NOT_CONVERGED, SUBSPACE_SMALL = 0, 1, 2
 EINVAL, EHIP, EWORKSPACE, EINTERVAL, ENUMERIC = -1, -2, -3, -4, -5
 PREC_FP64, PREC_MIXED = 0, 1
+FEATURE_R, FEATURE_MOMENTS = 16, 256
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 258, 128, 2, 49922
+NP_MIN, NP_MAX = 50, 20000
 
 P = ctypes.c_void_p
 i32, i64, f64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -33,6 +36,10 @@ class ChebfdParams(ctypes.Structure):
     ]
 
 
+class ChebfdPredictor(ctypes.Structure):
+    _fields_ = [("kappa", f64), ("t_mean", f64 * 2), ("t_std", f64 * 2)]
+
+
 class ChebfdStats(ctypes.Structure):
     _fields_ = [
         ("iterations", i32), ("n_found", i32), ("n_kept", i32), ("status", i32),
@@ -45,6 +52,7 @@ MP = ctypes.POINTER(ChebfdMatrix)
 PP = ctypes.POINTER(ChebfdParams)
 SP = ctypes.POINTER(ChebfdStats)
 DP = ctypes.POINTER(f64)
+FP = ctypes.POINTER(ctypes.c_float)
 
 # name -> (restype, argtypes); every symbol the header declares
 SIGNATURES = {
@@ -71,6 +79,15 @@ SIGNATURES = {
     "chebfd_heev": (ctypes.c_int, [i32, P, i32, P, i32, P, P, sz, P, ctypes.POINTER(i32)]),
     "chebfd_solve_query": (ctypes.c_int, [MP, MP, PP, ctypes.POINTER(sz)]),
     "chebfd_solve": (ctypes.c_int, [MP, MP, PP, P, P, sz, P, ctypes.POINTER(i32), P, P, P, SP]),
+    "chebfd_features_query": (ctypes.c_int, [MP, ctypes.POINTER(sz)]),
+    "chebfd_features": (ctypes.c_int, [MP, f64, f64, ctypes.c_uint64, FP, DP, DP, DP, P, sz, P]),
+    "chebfd_choose_params": (ctypes.c_int, [f64, f64, f64, i32, FP, ctypes.POINTER(ChebfdPredictor),
+                                            ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+    "chebfd_mlp_query": (ctypes.c_int, [i32, ctypes.POINTER(i32), ctypes.POINTER(sz)]),
+    "chebfd_mlp_forward": (ctypes.c_int, [P, i32, P, P, P, sz, P]),
+    "chebfd_mlp_grad": (ctypes.c_int, [P, i32, P, P, P, P, P, sz, P]),
+    "chebfd_mlp_adam": (ctypes.c_int, [P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, P]),
     "chebfd_probe_stream": (ctypes.c_int, [i32, i64, P, P, f64, P, P]),
 }
 

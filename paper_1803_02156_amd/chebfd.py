@@ -285,3 +285,81 @@ def chebfd_solve(H: Matrix, H64: Matrix, lam_L: float, lam_R: float, n_s: int, n
                                    _ptr(Z), resid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
     return SolveResult(status=rc, n_found=nf.value, theta=theta, resid=resid, Z=Z, stats=st,
                        workspace_bytes=sz.value)
+
+
+# ---------------------------------------------------------------------------
+# Parameter choice: moment features, heuristic / network -> (n_p, n_s)
+# ---------------------------------------------------------------------------
+def chebfd_features(H: Matrix, lam_L: float, lam_R: float, seed: int = 0):
+    """(features float32[258], count estimate, alpha, beta) of H and [lam_L, lam_R]."""
+    sz = ctypes.c_size_t()
+    check(load().chebfd_features_query(H.ref(), ctypes.byref(sz)))
+    work = device_buffer(sz.value, H.buf.device)
+    f = np.empty(_abi.MLP_IN, dtype=np.float32)
+    cnt, al, be = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    check(load().chebfd_features(H.ref(), lam_L, lam_R, seed, f.ctypes.data_as(_abi.FP), ctypes.byref(cnt),
+                                 ctypes.byref(al), ctypes.byref(be), _ptr(work), sz.value, _stream()))
+    return f, cnt.value, al.value, be.value
+
+
+def chebfd_choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, kappa: float = 1.0,
+                         t_mean=(0.0, 0.0), t_std=(1.0, 1.0)):
+    """(n_p, n_s) from the heuristic (mlp_out None) or the network's two outputs (host only)."""
+    pr = _abi.ChebfdPredictor()
+    pr.kappa = kappa
+    pr.t_mean[0], pr.t_mean[1] = t_mean
+    pr.t_std[0], pr.t_std[1] = t_std
+    out = None
+    if mlp_out is not None:
+        out = np.ascontiguousarray(np.asarray(mlp_out, dtype=np.float32)[:2])
+    n_p, n_s = ctypes.c_int32(), ctypes.c_int32()
+    check(load().chebfd_choose_params(a, b, count_est, n_b, None if out is None else out.ctypes.data_as(_abi.FP),
+                                      ctypes.byref(pr), ctypes.byref(n_p), ctypes.byref(n_s)))
+    return n_p.value, n_s.value
+
+
+def _mlp_work(batch: int, device):
+    sz = ctypes.c_size_t()
+    check(load().chebfd_mlp_query(batch, None, ctypes.byref(sz)))
+    return device_buffer(sz.value, device), sz.value
+
+
+def _f32(t: torch.Tensor, shape=None):
+    assert t.dtype == torch.float32 and t.is_contiguous() and t.is_cuda, "float32 contiguous CUDA tensor expected"
+    if shape is not None:
+        assert tuple(t.shape) == tuple(shape), (tuple(t.shape), shape)
+    return t
+
+
+def chebfd_mlp_forward(params: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Network outputs (batch, 2) for features x (batch, 258)."""
+    _f32(params, (_abi.MLP_PARAMS,))
+    batch = x.shape[0]
+    _f32(x, (batch, _abi.MLP_IN))
+    y = torch.empty((batch, _abi.MLP_OUT), dtype=torch.float32, device=x.device)
+    work, nbytes = _mlp_work(batch, x.device)
+    check(load().chebfd_mlp_forward(_ptr(params), batch, _ptr(x), _ptr(y), _ptr(work), nbytes, _stream()))
+    return y
+
+
+def chebfd_mlp_grad(params: torch.Tensor, x: torch.Tensor, t: torch.Tensor):
+    """(loss (1,), gradient (n_params,)) of sum ||y - t||^2 / (2 batch)."""
+    _f32(params, (_abi.MLP_PARAMS,))
+    batch = x.shape[0]
+    _f32(x, (batch, _abi.MLP_IN))
+    _f32(t, (batch, _abi.MLP_OUT))
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty_like(params)
+    work, nbytes = _mlp_work(batch, x.device)
+    check(load().chebfd_mlp_grad(_ptr(params), batch, _ptr(x), _ptr(t), _ptr(loss), _ptr(grad), _ptr(work),
+                                 nbytes, _stream()))
+    return loss, grad
+
+
+def chebfd_mlp_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
+                    lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step in place on params, m, v."""
+    for t in (params, grad, m, v):
+        _f32(t, (_abi.MLP_PARAMS,))
+    check(load().chebfd_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                                 _stream()))

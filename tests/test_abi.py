@@ -94,3 +94,40 @@ def test_filter_rejects_null_handle(lib):
 def test_probe_rejects_bad_args(lib):
     assert lib.chebfd_probe_stream(2, 16, None, None, 1.0, None, None) == -1
     assert lib.chebfd_probe_stream(0, 15, None, None, 1.0, None, None) == -1
+
+
+@pytest.mark.parametrize("a,b,cnt,n_b,out", [
+    (-0.01, 0.01, 47.3, 32, None), (-0.3, 0.25, 3.0, 16, None), (-0.9, 0.9, 1e6, 32, None),
+    (-1e-6, 1e-6, -2.0, 8, None), (-0.02, 0.05, 10.0, 32, (0.3, -1.2)), (-0.02, 0.05, 400.0, 64, (9.0, 9.0)),
+    (-0.5, 0.5, 0.0, 128, (-40.0, -40.0)),
+])
+def test_choose_params_matches_oracle(a, b, cnt, n_b, out):
+    import paper_1803_02156_amd as P
+    import oracle as O
+    kw = dict(kappa=1.7, t_mean=(6.0, 4.0), t_std=(1.3, 0.8))
+    got = P.chebfd_choose_params(a, b, cnt, n_b, out, **kw)
+    if out is not None:
+        out = np.asarray(out, dtype=np.float32)
+    ref = O.choose_params(a, b, cnt, n_b, out, **kw)
+    assert got == ref
+    n_p, n_s = got
+    assert 50 <= n_p <= 20000 and n_s % n_b == 0 and n_b <= n_s <= max(n_b, 512)
+
+
+def test_choose_params_rejects_bad_args():
+    import paper_1803_02156_amd as P
+    for args in [(0.1, -0.1, 1.0, 32), (-1.0, 0.5, 1.0, 32), (-0.1, 0.1, float("nan"), 32), (-0.1, 0.1, 1.0, 3)]:
+        with pytest.raises(P.ChebfdError) as e:
+            P.chebfd_choose_params(*args)
+        assert e.value.code == -1
+    with pytest.raises(P.ChebfdError):
+        P.chebfd_choose_params(-0.1, 0.1, 1.0, 32, kappa=0.0)
+
+
+def test_mlp_query_sizes(lib):
+    n = ctypes.c_int32()
+    sz = ctypes.c_size_t()
+    assert lib.chebfd_mlp_query(2000, ctypes.byref(n), ctypes.byref(sz)) == 0
+    assert n.value == 128 * 258 + 128 + 128 * 128 + 128 + 2 * 128 + 2
+    assert sz.value >= 4 * 2000 * (4 * 128 + 2 * 2)
+    assert lib.chebfd_mlp_query(0, ctypes.byref(n), ctypes.byref(sz)) == -1

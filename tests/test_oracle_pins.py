@@ -300,3 +300,13 @@ def test_solve_small_configuration_matches_shift_invert():
     assert res.status == 0 and res.n_found == len(ref)
     assert np.max(np.abs(res.theta[:res.n_found] - ref)) < 1e-12
     assert np.max(res.resid[:res.n_found]) <= 1e-9
+
+
+def test_choose_params_reading():
+    # heuristic: n_p = kappa / half width, n_s = 2 n_hat rounded up to a block
+    assert O.choose_params(-0.01, 0.01, 47.3, 32, kappa=2.0) == (200, 96)
+    assert O.choose_params(-0.5, 0.5, 0.0, 16, kappa=2.0) == (50, 16)           # both floors
+    assert O.choose_params(-1e-5, 1e-5, 1e4, 32, kappa=2.0) == (20000, 512)     # both ceilings
+    # network outputs are de-standardised logs; n_s kept >= 1.2 n_hat
+    n_p, n_s = O.choose_params(-0.1, 0.1, 100.0, 32, mlp_out=(0.0, 0.0), t_mean=(np.log(800.0), np.log(40.0)))
+    assert n_p == 800 and n_s == 128
