@@ -9,12 +9,15 @@ Inputs are synthetic and resident in HBM before the timed region.
 
 Prints one JSON line: the filter's algorithmic HBM bandwidth (the paper's
 minimum-traffic model, Sect. 3.4) as `value`, the roofline of the fused step
-kernel, and the FP64 CPU oracle timed on a bounded sample of the same workload
-on the host cores.
+kernel (its launches timed on their own), the time to converged Ritz pairs of
+the whole iteration in FP64 and in mixed precision on the same matrix, and the
+FP64 CPU oracle timed on a bounded sample of the same workload on the host
+cores.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -42,7 +45,96 @@ def parse():
     ap.add_argument("--prec", type=int, default=0, help="0 = FP64, 1 = mixed (c64 storage)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables)")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-converged leg")
+    ap.add_argument("--solve-count", type=float, default=100.0,
+                    help="eigenvalue count the symmetric search interval is sized for")
+    ap.add_argument("--op-launches", type=int, default=200, help="launches of the fused step timed alone")
     return ap.parse_args()
+
+
+KERNEL_SRC = os.path.join(HERE, "paper_1803_02156_amd", "csrc", "filter_lds.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def counter_traffic(prec: int, n_b: int, lattice: str):
+    """HBM bytes per fused-step launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, if it was taken on the current kernel source; else None."""
+    name = f"traffic_cheb_lds_step_topi{lattice.replace('x', '-')}_{'fp64' if prec == 0 else 'mixed'}_nb{n_b}.json"
+    path = os.path.join(HERE, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
+def interval_for_count(P, M, target, seed=7):
+    """Half width delta of the symmetric interval [-delta, delta] whose KPM count
+    estimate (256 moments, 16 random-phase vectors) is closest to `target`."""
+    lo_b, hi_b = P.chebfd_bounds(M)
+    half = max(abs(lo_b), abs(hi_b))
+    a, b = 1e-4 * half, 0.5 * half
+    cache = {}
+
+    def count(d):
+        if d not in cache:
+            cache[d] = P.chebfd_features(M, -d, d, seed)[1]
+        return cache[d]
+    for _ in range(40):
+        mid = 0.5 * (a + b)
+        if count(mid) < target:
+            a = mid
+        else:
+            b = mid
+        if b - a < 1e-4 * b:
+            break
+    return 0.5 * (a + b), count(0.5 * (a + b))
+
+
+def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target):
+    """Full ChebFD runs (filter, SVQB, Rayleigh-Ritz, residuals, restarts) in FP64 and
+    mixed precision on the same matrix and interval; wall time from the first launch
+    to the synchronised end, matrix build excluded."""
+    import torch
+    M64 = P.chebfd_matrix_build(*H, prec=0)
+    delta, cnt = interval_for_count(P, M64, target)
+    out = {"workload": f"Topi-{Nx}-{Ny}-{Nz} (W={W}), interval [-{delta:.6g}, {delta:.6g}] "
+                       f"(KPM count estimate {cnt:.1f}), n_s={n_s}, n_b={n_b}, n_p={n_p}",
+           "interval": [-delta, delta], "count_est_kpm": cnt}
+    runs = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        M = M64 if prec == 0 else P.chebfd_matrix_build(*H, prec=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = P.chebfd_solve(M, M64, -delta, delta, n_s, n_p, n_b, seed=43, max_iter=12, want_vectors=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nf = r.n_found
+        runs[name] = r
+        st = r.stats
+        out[name] = {
+            "seconds": round(dt, 3), "status": r.status, "iterations": st.iterations, "n_found": nf,
+            "max_resid": float(np.max(r.resid[:nf])) if nf else None,
+            "tol": 1e-9 if prec == 0 else 1e-7,
+            "t_filter": round(st.t_filter, 3), "t_orth": round(st.t_orth, 3), "t_rr": round(st.t_rr, 3),
+            "t_resid": round(st.t_resid, 3),
+            "filter_gbs": round(st.filter_bytes / st.t_filter / 1e9, 1) if st.t_filter > 0 else None,
+        }
+        print(f"# solve {name}: {dt:.2f} s, status {r.status}, {st.iterations} iterations, "
+              f"{nf} pairs", file=sys.stderr, flush=True)
+        del M
+    a, b = runs["fp64"], runs["mixed"]
+    if a.n_found == b.n_found and a.n_found > 0:
+        out["mixed"]["max_abs_dtheta_vs_fp64"] = float(np.max(np.abs(np.sort(a.theta[:a.n_found]) -
+                                                                      np.sort(b.theta[:b.n_found]))))
+    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    return out
 
 
 def oracle_sample(H, n, nnz, n_b, prec, target_s):
@@ -137,12 +229,24 @@ def main():
     fbytes = traffic.filter_bytes(n, nnz, n_s, n_b, n_p, prec)
     gbs = fbytes / (filt_ms * 1e-3) / 1e9
     gflops = traffic.filter_flops(n, n_s, n_p, nnz / n) / (filt_ms * 1e-3) / 1e9
-    # dominant kernel: the fused step; launches per filter = blocks * n_p (all the same
-    # sparse pass: n_p - 2 fused steps and the two start launches)
-    launches = (n_s // n_b) * n_p
-    avg_launch_s = filt_ms * 1e-3 / launches
+    # dominant kernel: the fused step (n_p - 2 of every n_p launches of a block), timed
+    # alone: op_launches launches on three blocks of the start block, events on the stream
+    xv = xy.view(n_s // n_b, n, n_b)
+    opw = P.device_buffer(P.chebfd_filter_query(M, n_b))
+    opb = opw.numel()
+    P.chebfd_op(M, al, be, gam[3], n_b, xv[0], xv[1], xv[2], opw, opb)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.op_launches):
+        P.chebfd_op(M, al, be, gam[3], n_b, xv[0], xv[1], xv[2], opw, opb)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    avg_launch_s = e0.elapsed_time(e1) * 1e-3 / args.op_launches
     r, w = traffic.step_bytes(n, nnz, n_b, prec)
     achieved = (r + w) / avg_launch_s / 1e9
+    hbm = counter_traffic(prec, n_b, args.lattice)
+    del opw
 
     # attainable HBM bandwidth: copy probe over 2 x 2 GiB (the STREAM analogue of Table 2)
     cnt = 1 << 28
@@ -157,6 +261,12 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 10 * 2 * 8 * cnt / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del pa, pb
+
+    solve = None
+    if not args.no_solve:
+        del xy, xb0, work
+        torch.cuda.empty_cache()
+        solve = time_to_converged(P, H, Nx, Ny, Nz, args.W, n_s, n_b, n_p, args.solve_count)
 
     cpu = None
     if args.cpu_baseline_seconds > 0:
@@ -190,10 +300,12 @@ def main():
         "pct_of_copy_probe": round(100.0 * gbs / copy_gbs, 2),
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"cheb_step_kernel<{'double' if prec == 0 else 'float'},{n_b},2>",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": hbm,
+            "kernel": f"cheb_lds_kernel<{'double' if prec == 0 else 'float'},{n_b},kModeStep>",
             "bytes_per_launch": r + w, "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "kernel_source_sha256_16": kernel_source_hash(),
         },
+        "time_to_converged": solve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

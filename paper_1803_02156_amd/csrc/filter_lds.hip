@@ -143,22 +143,34 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
         stride = G;
     }
 
-    // prefetch registers for one tile's slots
-    VT pv[PF];
+    // prefetch registers for one tile's slots (plain scalars: arrays of HIP
+    // vector structs are not promoted to registers and would live in scratch)
+    T pvr[PF], pvi[PF];
     int32_t pc[PF];
     int64_t pf_s0 = 0;
     int pf_ns = 0;
+    // Equally wide chunks (every row padded to uw slots): chunk c starts at
+    // slot c C uw, so no chunk metadata is read (a load of it would make the
+    // wave wait for all its outstanding stores before the next tile).
+    const int uw = a.uniform_width;
     auto fetch = [&](int64_t tile) {
         const int64_t c0 = (tile * tile_rows) >> a.log2C;
         int64_t c1 = c0 + cpt;
         if (c1 > a.n_chunks) c1 = a.n_chunks;
-        pf_s0 = a.chunk_off[c0];
-        pf_ns = static_cast<int>(a.chunk_off[c1] - pf_s0);
+        if (uw > 0) {
+            pf_s0 = c0 * a.C * uw;
+            pf_ns = static_cast<int>((c1 - c0) * a.C * uw);
+        } else {
+            pf_s0 = a.chunk_off[c0];
+            pf_ns = static_cast<int>(a.chunk_off[c1] - pf_s0);
+        }
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int s = tid + q * kThreads;
             if (s < pf_ns) {
-                pv[q] = gval[pf_s0 + s];
+                const VT v = gval[pf_s0 + s];
+                pvr[q] = v.x;
+                pvi[q] = v.y;
                 pc[q] = gcol[pf_s0 + s];
             }
         }
@@ -169,10 +181,11 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
         for (int q = 0; q < PF; ++q) {
             const int s = tid + q * kThreads;
             if (s < pf_ns) {
-                CHEBFD_SV(b)[s] = pv[q];
+                CHEBFD_SV(b)[s] = VT{pvr[q], pvi[q]};
                 CHEBFD_SC(b)[s] = pc[q];
             }
         }
+        if (uw > 0) return;
         for (int q = tid; q < cpt; q += kThreads) {
             const int64_t c = c0 + q;
             const bool in = c < a.n_chunks;
@@ -198,12 +211,12 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
         const int32_t *scwb = CHEBFD_SCW(buf);
         const int64_t t0 = tile * tile_rows;
         for (int sp = 0; sp < tile_rows; sp += ROWS) {
-            const int r = sp + rr;           // row within the tile
-            const int64_t i = t0 + r;
-            if (i >= a.n) continue;
+          const int r = sp + rr;             // row within the tile
+          const int64_t i = t0 + r;
+          if (i < a.n) {
             const int cl = r >> a.log2C;
-            const int base = scoffb[cl] + (r & (a.C - 1));
-            const int wdt = scwb[cl];
+            const int base = (uw > 0 ? cl * a.C * uw : scoffb[cl]) + (r & (a.C - 1));
+            const int wdt = uw > 0 ? uw : scwb[cl];
             const int64_t e = i * NB + j;
 
             // row streams (U_i is also gathered by neighbours: cached; W, Y: streamed)
@@ -281,12 +294,14 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
             e_re = fma(nr, ur, fma(ni, ui, e_re));
             e_im = fma(nr, ui, fma(-ni, ur, e_im));
             nu = fma(ur, ur, fma(ui, ui, nu));
+          }
+          // The next tile's slots go to the idle buffer after the first
+          // sub-pass: their loads have landed by then, and the wait for them
+          // does not cover the stores of the later sub-passes.
+          if (sp == 0 && more) deposit(tile + stride, buf ^ 1);
         }
 
-        if (more) {
-            deposit(tile + stride, buf ^ 1);
-            buf ^= 1;
-        }
+        if (more) buf ^= 1;
         __syncthreads();
     }
 

@@ -1,0 +1,284 @@
+"""Learned choice of the filter degree n_p and the subspace size n_s.
+
+The paper sets n_p and n_s by hand (Sect. 2: n_s somewhat above the number of
+wanted eigenpairs; Sect. 5: n_p around 10^3 for its matrices) and notes that
+the filter's dot products are KPM moments, i.e. a cheap picture of the
+spectrum (Sect. 2).  This module turns that picture into the two parameters:
+
+* features: ``chebfd_features`` (256 normalised moments from 16 random-phase
+  vectors plus the scaled interval [a~, b~]);
+* the fallback heuristic of ``chebfd_choose_params`` (n_p = kappa / delta,
+  n_s = 2 n_hat);
+* a 258-128-128-2 network trained with the library's own device kernels
+  (``chebfd_mlp_grad`` / ``chebfd_mlp_adam``) on runs of the method itself.
+
+Labels: for each instance a small grid of (n_p, n_s) around the heuristic is
+solved, and the label is the grid point with the least deterministic work
+``iters (n_p n_s nnz + c_orth n n_s^2)`` among the runs that converged with the
+full eigenvalue count; the network regresses the standardised
+(log n_p, log n_s) of that point.
+
+Every computation runs in libchebfd; this file only orchestrates runs and
+stores their results (numpy on the host).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _abi
+from . import chebfd as P
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "data", "predictor.npz")
+
+C_ORTH = 8.0          # relative weight of the dense O(n n_s^2) work per iteration
+N_B = 32
+
+
+@dataclass
+class Instance:
+    dims: tuple
+    m: float
+    W: float
+    half_width: float      # search interval [-hw, hw] in H's units
+    seed: int
+
+
+def sample_instance(rng: np.random.Generator, ext_lo: int, ext_hi: int, seed: int) -> Instance:
+    """A Topi instance: extents in [ext_lo, ext_hi] with a random aspect ratio,
+    m ~ U[0.5, 2.5], W ~ U[0, 3], interval half width ~ U[0.01, 0.1]."""
+    dims = tuple(int(v) for v in rng.integers(ext_lo, ext_hi + 1, 3))
+    return Instance(dims=dims, m=float(rng.uniform(0.5, 2.5)), W=float(rng.uniform(0.0, 3.0)),
+                    half_width=float(rng.uniform(0.01, 0.1)), seed=int(seed))
+
+
+def build(inst: Instance, prec: int = _abi.PREC_FP64):
+    from topi import topi_csr
+    H = topi_csr(*inst.dims, m=inst.m, W=inst.W, seed=inst.seed)
+    return H, P.chebfd_matrix_build(*H, prec=prec)
+
+
+def work_units(n: int, nnz: int, n_p: int, n_s: int, iters: int) -> float:
+    """Deterministic cost of a run: filter row-column products plus the dense part."""
+    return float(iters) * (n_p * n_s * (nnz / n) * n + C_ORTH * n * n_s * n_s)
+
+
+def run(M, inst: Instance, n_p: int, n_s: int, max_iter: int = 12):
+    t0 = time.perf_counter()
+    r = P.chebfd_solve(M, M, -inst.half_width, inst.half_width, n_s, n_p, N_B, seed=43 + inst.seed,
+                       max_iter=max_iter, want_vectors=False)
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def grid(heur_np: int, heur_ns: int):
+    nps = sorted({int(min(_abi.NP_MAX, max(_abi.NP_MIN, round(heur_np * f)))) for f in (0.5, 1.0, 2.0)})
+    nss = sorted({heur_ns, min(512, heur_ns + N_B)})
+    return [(a, b) for a in nps for b in nss]
+
+
+def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, log=print):
+    """Features, heuristic choice, grid runs and labels of `count` instances."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for k in range(count):
+        inst = sample_instance(rng, ext_lo, ext_hi, seed * 100000 + k)
+        H, M = build(inst)
+        n, nnz = M.n, len(H[1])
+        f, cnt, al, be = P.chebfd_features(M, -inst.half_width, inst.half_width, seed=7 + k)
+        a, b = f[256], f[257]
+        hp, hs = P.chebfd_choose_params(float(a), float(b), cnt, N_B, kappa=kappa)
+        results = []
+        for n_p, n_s in grid(hp, hs):
+            r, dt = run(M, inst, n_p, n_s)
+            results.append(dict(n_p=n_p, n_s=n_s, status=r.status, iters=r.stats.iterations,
+                                n_found=r.n_found, seconds=dt,
+                                work=work_units(n, nnz, n_p, n_s, r.stats.iterations)))
+        full = max(x["n_found"] for x in results)
+        ok = [x for x in results if x["status"] == 0 and x["n_found"] == full]
+        best = min(ok, key=lambda x: x["work"]) if ok else None
+        rows.append(dict(inst=inst.__dict__, n=n, nnz=nnz, features=f.tolist(), count_est=cnt,
+                         heuristic=(hp, hs), runs=results, full_count=full,
+                         label=None if best is None else (best["n_p"], best["n_s"])))
+        log(f"# corpus {k + 1}/{count}: dims {inst.dims} n={n} count~{cnt:.1f} found {full} "
+            f"heur ({hp},{hs}) label {rows[-1]['label']}")
+    return rows
+
+
+def standardise(labels: np.ndarray):
+    lg = np.log(labels.astype(np.float64))
+    mean = lg.mean(axis=0)
+    std = np.maximum(lg.std(axis=0), 1e-3)
+    return (lg - mean) / std, mean, std
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, in the library's flat layout."""
+    rng = np.random.default_rng(seed)
+    shapes = [(_abi.MLP_HIDDEN, _abi.MLP_IN), (_abi.MLP_HIDDEN,), (_abi.MLP_HIDDEN, _abi.MLP_HIDDEN),
+              (_abi.MLP_HIDDEN,), (_abi.MLP_OUT, _abi.MLP_HIDDEN), (_abi.MLP_OUT,)]
+    parts = [rng.standard_normal(s).ravel() * math.sqrt(2.0 / s[1]) if len(s) == 2 else np.zeros(s)
+             for s in shapes]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(X: np.ndarray, T: np.ndarray, steps: int = 3000, lr: float = 1e-3, seed: int = 0, log=print):
+    """Full-batch Adam on the device kernels; returns the flat parameters (numpy)."""
+    p = torch.from_numpy(init_params(seed)).cuda()
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    x = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    t = torch.from_numpy(np.ascontiguousarray(T, dtype=np.float32)).cuda()
+    for step in range(1, steps + 1):
+        loss, g = P.chebfd_mlp_grad(p, x, t)
+        P.chebfd_mlp_adam(p, g, m, v, step, lr=lr)
+        if step % 500 == 0 or step == 1:
+            log(f"# train step {step}: loss {loss.item():.4f}")
+    return p.cpu().numpy()
+
+
+def predict(params: np.ndarray, features: np.ndarray) -> np.ndarray:
+    p = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(np.atleast_2d(features), dtype=np.float32)).cuda()
+    return P.chebfd_mlp_forward(p, x).cpu().numpy()
+
+
+def save(path: str, params: np.ndarray, mean, std, kappa: float, meta: dict):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, params=params.astype(np.float32), t_mean=np.asarray(mean), t_std=np.asarray(std),
+             kappa=np.asarray(kappa), meta=np.asarray(json.dumps(meta)))
+
+
+def load(path: str = DEFAULT_WEIGHTS):
+    z = np.load(path, allow_pickle=False)
+    return dict(params=z["params"], t_mean=tuple(z["t_mean"]), t_std=tuple(z["t_std"]),
+                kappa=float(z["kappa"]), meta=json.loads(str(z["meta"])))
+
+
+def choose(pred: dict | None, features: np.ndarray, count_est: float, kappa: float):
+    """(n_p, n_s): the network's choice if `pred` is given, else the heuristic."""
+    a, b = float(features[256]), float(features[257])
+    if pred is None:
+        return P.chebfd_choose_params(a, b, count_est, N_B, kappa=kappa)
+    out = predict(pred["params"], features)[0]
+    return P.chebfd_choose_params(a, b, count_est, N_B, out, kappa=kappa, t_mean=pred["t_mean"],
+                                  t_std=pred["t_std"])
+
+
+def evaluate(pred: dict, corpus: list, kappa: float, log=print):
+    """Solve every instance with the heuristic's and with the network's (n_p, n_s);
+    compare iterations, work, wall time and failures (a run that is not converged
+    or finds fewer pairs than the instance's full count)."""
+    out = []
+    for k, row in enumerate(corpus):
+        inst = Instance(**{**row["inst"], "dims": tuple(row["inst"]["dims"])})
+        H, M = build(inst)
+        f = np.asarray(row["features"], dtype=np.float32)
+        res = {}
+        for name, pr in (("heuristic", None), ("mlp", pred)):
+            n_p, n_s = choose(pr, f, row["count_est"], kappa)
+            r, dt = run(M, inst, n_p, n_s)
+            res[name] = dict(n_p=n_p, n_s=n_s, status=r.status, iters=r.stats.iterations, n_found=r.n_found,
+                             seconds=dt, work=work_units(M.n, len(H[1]), n_p, n_s, r.stats.iterations),
+                             failed=bool(r.status != 0 or r.n_found < row["full_count"]))
+        out.append(dict(inst=row["inst"], full_count=row["full_count"], **res))
+        log(f"# eval {k + 1}/{len(corpus)}: heur {res['heuristic']['n_p']},{res['heuristic']['n_s']} "
+            f"it {res['heuristic']['iters']} {res['heuristic']['seconds']:.3f}s | mlp {res['mlp']['n_p']},"
+            f"{res['mlp']['n_s']} it {res['mlp']['iters']} {res['mlp']['seconds']:.3f}s")
+    return out
+
+
+def summarise(ev: list) -> dict:
+    def col(name, key):
+        return np.array([e[name][key] for e in ev], dtype=np.float64)
+    s = {"instances": len(ev)}
+    for name in ("heuristic", "mlp"):
+        s[name] = {"failures": int(sum(e[name]["failed"] for e in ev)),
+                   "mean_iters": float(col(name, "iters").mean()),
+                   "total_seconds": float(col(name, "seconds").sum()),
+                   "total_work": float(col(name, "work").sum())}
+    ok = [e for e in ev if not e["heuristic"]["failed"] and not e["mlp"]["failed"]]
+    if ok:
+        rw = np.array([e["mlp"]["work"] / e["heuristic"]["work"] for e in ok])
+        rt = np.array([e["mlp"]["seconds"] / e["heuristic"]["seconds"] for e in ok])
+        s["work_ratio_mlp_over_heuristic"] = {"mean": float(rw.mean()), "median": float(np.median(rw))}
+        s["time_ratio_mlp_over_heuristic"] = {"mean": float(rt.mean()), "median": float(np.median(rt))}
+    return s
+
+
+def calibrate_kappa(inst: Instance, n_s: int, factors=(0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0), log=print):
+    """kappa = n_p delta~ of the least-work converged run on one instance (the
+    heuristic's constant, fixed once and stored with the weights)."""
+    H, M = build(inst)
+    lo, hi = P.chebfd_bounds(M)
+    delta = inst.half_width * 2.0 / (hi - lo)
+    best = None
+    for kf in factors:
+        n_p = int(round(kf / delta))
+        r, dt = run(M, inst, n_p, n_s, max_iter=20)
+        w = work_units(M.n, len(H[1]), n_p, n_s, r.stats.iterations)
+        log(f"# kappa {kf}: n_p {n_p} status {r.status} iters {r.stats.iterations} found {r.n_found} "
+            f"{dt:.2f}s work {w:.3e}")
+        if r.status == 0 and (best is None or w < best[1]):
+            best = (kf, w)
+    return best[0] if best else 1.0
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="corpus / training / evaluation of the parameter predictor")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("corpus")
+    c.add_argument("--count", type=int, required=True)
+    c.add_argument("--seed", type=int, required=True)
+    c.add_argument("--ext", type=int, nargs=2, default=(12, 24))
+    c.add_argument("--kappa", type=float, required=True)
+    c.add_argument("--out", required=True)
+    k = sub.add_parser("kappa")
+    k.add_argument("--dims", type=int, nargs=3, default=(16, 16, 8))
+    t = sub.add_parser("train")
+    t.add_argument("--corpus", nargs="+", required=True)
+    t.add_argument("--kappa", type=float, required=True)
+    t.add_argument("--steps", type=int, default=3000)
+    t.add_argument("--out", default=DEFAULT_WEIGHTS)
+    e = sub.add_parser("eval")
+    e.add_argument("--corpus", nargs="+", required=True)
+    e.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    e.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    assert torch.cuda.is_available(), "the predictor runs on the GPU"
+    P.load()
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    if a.cmd == "kappa":
+        inst = Instance(dims=tuple(a.dims), m=1.0, W=1.0, half_width=0.05, seed=1001)
+        log(json.dumps({"kappa": calibrate_kappa(inst, 32, log=log)}))
+    elif a.cmd == "corpus":
+        rows = make_corpus(a.count, a.seed, a.ext[0], a.ext[1], a.kappa, log=log)
+        with open(a.out, "w") as f:
+            json.dump(rows, f)
+    elif a.cmd == "train":
+        rows = [r for p in a.corpus for r in json.load(open(p)) if r["label"] is not None]
+        X = np.array([r["features"] for r in rows], dtype=np.float32)
+        T, mean, std = standardise(np.array([r["label"] for r in rows], dtype=np.float64))
+        params = train(X, T, steps=a.steps, log=log)
+        save(a.out, params, mean, std, a.kappa, {"train_instances": len(rows), "steps": a.steps,
+                                                  "corpus": [os.path.basename(p) for p in a.corpus]})
+        log(f"# saved {a.out}")
+    elif a.cmd == "eval":
+        rows = [r for p in a.corpus for r in json.load(open(p))]
+        pred = load(a.weights)
+        ev = evaluate(pred, rows, pred["kappa"], log=log)
+        summ = summarise(ev)
+        with open(a.out, "w") as f:
+            json.dump({"summary": summ, "runs": ev}, f, indent=1)
+        log(json.dumps(summ))
+
+
+if __name__ == "__main__":
+    main()
