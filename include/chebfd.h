@@ -97,12 +97,18 @@ int chebfd_device_info(int32_t *num_cus, char *name, int32_t name_len);
  *   h_val[2*nnz] interleaved c128.  The matrix must be Hermitian (not checked).
  *   C in {1..1024}, sigma >= 1 and a multiple of C (or 1); prec per CHEBFD_PREC_*.
  *   d_buf must be 256-byte aligned.
+ *   h_order (optional, NULL = natural order): a permutation of 0..n-1 giving the
+ *   row order before the sigma sort (h_order[k] = original row placed k-th), a
+ *   further symmetric permutation, e.g. one that keeps the rows a step gathers
+ *   close together in memory.  Results do not depend on it beyond rounding
+ *   order: vectors enter and leave through chebfd_pack/unpack in the original
+ *   numbering, and device-drawn random vectors are keyed by original rows.
  */
-int chebfd_matrix_query(int64_t n, const int64_t *h_rowptr, int32_t C, int32_t sigma,
-                        int32_t prec, size_t *bytes);
+int chebfd_matrix_query(int64_t n, const int64_t *h_rowptr, const int32_t *h_order, int32_t C,
+                        int32_t sigma, int32_t prec, size_t *bytes);
 int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col,
-                        const double *h_val, int32_t C, int32_t sigma, int32_t prec,
-                        void *d_buf, size_t bytes, void *stream, chebfd_matrix *out);
+                        const double *h_val, const int32_t *h_order, int32_t C, int32_t sigma,
+                        int32_t prec, void *d_buf, size_t bytes, void *stream, chebfd_matrix *out);
 
 /*
  * Gershgorin bounds of H (the interval that must be mapped onto [-1, 1] by the

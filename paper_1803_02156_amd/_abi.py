@@ -59,8 +59,8 @@ SIGNATURES = {
     "chebfd_version": (ctypes.c_int, []),
     "chebfd_last_error": (ctypes.c_char_p, []),
     "chebfd_device_info": (ctypes.c_int, [ctypes.POINTER(i32), ctypes.c_char_p, i32]),
-    "chebfd_matrix_query": (ctypes.c_int, [i64, P, i32, i32, i32, ctypes.POINTER(sz)]),
-    "chebfd_matrix_build": (ctypes.c_int, [i64, P, P, P, i32, i32, i32, P, sz, P, MP]),
+    "chebfd_matrix_query": (ctypes.c_int, [i64, P, P, i32, i32, i32, ctypes.POINTER(sz)]),
+    "chebfd_matrix_build": (ctypes.c_int, [i64, P, P, P, P, i32, i32, i32, P, sz, P, MP]),
     "chebfd_bounds_query": (ctypes.c_int, [MP, ctypes.POINTER(sz)]),
     "chebfd_bounds": (ctypes.c_int, [MP, P, sz, P, DP, DP]),
     "chebfd_coefficients": (ctypes.c_int, [f64, f64, f64, f64, i32, DP, DP, P]),

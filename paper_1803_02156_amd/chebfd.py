@@ -67,24 +67,36 @@ def chebfd_device_info():
     return n.value, name.value.decode()
 
 
-def chebfd_matrix_query(rowptr, C=32, sigma=256, prec=PREC_FP64) -> int:
+def _order_arg(order, n):
+    if order is None:
+        return None, None
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    if o.shape != (n,):
+        raise ValueError("order must hold n row indices")
+    return o, o.ctypes.data_as(ctypes.c_void_p)
+
+
+def chebfd_matrix_query(rowptr, C=32, sigma=256, prec=PREC_FP64, order=None) -> int:
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    keep, op = _order_arg(order, len(rowptr) - 1)
     b = ctypes.c_size_t()
-    check(load().chebfd_matrix_query(len(rowptr) - 1, rowptr.ctypes.data_as(ctypes.c_void_p),
+    check(load().chebfd_matrix_query(len(rowptr) - 1, rowptr.ctypes.data_as(ctypes.c_void_p), op,
                                      C, sigma, prec, ctypes.byref(b)))
     return b.value
 
 
-def chebfd_matrix_build(rowptr, col, val, C=32, sigma=256, prec=PREC_FP64, device="cuda") -> Matrix:
-    """Build the device matrix from host CRS arrays (int64 rowptr, int32 col, complex128 val)."""
+def chebfd_matrix_build(rowptr, col, val, C=32, sigma=256, prec=PREC_FP64, device="cuda", order=None) -> Matrix:
+    """Build the device matrix from host CRS arrays (int64 rowptr, int32 col, complex128 val);
+    `order` optionally gives the row order (a permutation of 0..n-1) before the sigma sort."""
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
     col = np.ascontiguousarray(col, dtype=np.int32)
     val = np.ascontiguousarray(val, dtype=np.complex128)
-    nbytes = chebfd_matrix_query(rowptr, C, sigma, prec)
+    keep, op = _order_arg(order, len(rowptr) - 1)
+    nbytes = chebfd_matrix_query(rowptr, C, sigma, prec, order=keep)
     buf = device_buffer(nbytes, device)
     h = _abi.ChebfdMatrix()
     vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
-    check(load().chebfd_matrix_build(len(rowptr) - 1, vp(rowptr), vp(col), vp(val), C, sigma, prec,
+    check(load().chebfd_matrix_build(len(rowptr) - 1, vp(rowptr), vp(col), vp(val), op, C, sigma, prec,
                                      _ptr(buf), nbytes, _stream(), ctypes.byref(h)))
     return Matrix(h, buf)
 

@@ -83,10 +83,27 @@ static int check_matrix_args(int64_t n, const int64_t *rowptr, int32_t C, int32_
     return CHEBFD_OK;
 }
 
-static void make_plan(int64_t n, const int64_t *rowptr, int32_t C, int32_t sigma, SellPlan &p) {
+static int check_order(int64_t n, const int32_t *order) {
+    if (!order) return CHEBFD_OK;
+    std::vector<char> seen(n, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        CHEBFD_REQUIRE(order[k] >= 0 && order[k] < n && !seen[order[k]],
+                       "h_order is not a permutation of 0..n-1 (entry %lld)", (long long)k);
+        seen[order[k]] = 1;
+    }
+    return CHEBFD_OK;
+}
+
+// Row order of the SELL matrix: the caller's order (or the natural one), then
+// a stable sort by row length inside each window of sigma rows.
+static void make_plan(int64_t n, const int64_t *rowptr, const int32_t *order, int32_t C, int32_t sigma,
+                      SellPlan &p) {
     p.n = n;
     p.perm.resize(n);
-    std::iota(p.perm.begin(), p.perm.end(), 0);
+    if (order)
+        std::copy(order, order + n, p.perm.begin());
+    else
+        std::iota(p.perm.begin(), p.perm.end(), 0);
     auto len = [&](int32_t r) { return rowptr[r + 1] - rowptr[r]; };
     if (sigma > 1) {
         for (int64_t w0 = 0; w0 < n; w0 += sigma) {
@@ -157,24 +174,24 @@ int chebfd_device_info(int32_t *num_cus, char *name, int32_t name_len) {
     return CHEBFD_OK;
 }
 
-int chebfd_matrix_query(int64_t n, const int64_t *h_rowptr, int32_t C, int32_t sigma,
-                        int32_t prec, size_t *bytes) {
+int chebfd_matrix_query(int64_t n, const int64_t *h_rowptr, const int32_t *h_order, int32_t C,
+                        int32_t sigma, int32_t prec, size_t *bytes) {
     clear_error();
     int rc = check_matrix_args(n, h_rowptr, C, sigma, prec);
-    if (rc) return rc;
+    if (rc || (rc = check_order(n, h_order))) return rc;
     CHEBFD_REQUIRE(bytes != nullptr, "bytes is NULL");
     SellPlan p;
-    make_plan(n, h_rowptr, C, sigma, p);
+    make_plan(n, h_rowptr, h_order, C, sigma, p);
     *bytes = matrix_layout(p, prec, C).total;
     return CHEBFD_OK;
 }
 
 int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col,
-                        const double *h_val, int32_t C, int32_t sigma, int32_t prec, void *d_buf,
-                        size_t bytes, void *stream, chebfd_matrix *out) {
+                        const double *h_val, const int32_t *h_order, int32_t C, int32_t sigma,
+                        int32_t prec, void *d_buf, size_t bytes, void *stream, chebfd_matrix *out) {
     clear_error();
     int rc = check_matrix_args(n, h_rowptr, C, sigma, prec);
-    if (rc) return rc;
+    if (rc || (rc = check_order(n, h_order))) return rc;
     const int64_t nnz = h_rowptr[n];
     CHEBFD_REQUIRE(nnz == 0 || (h_col && h_val), "h_col / h_val is NULL");
     CHEBFD_REQUIRE(d_buf != nullptr && aligned(d_buf, 256), "d_buf must be non-NULL and 256-byte aligned");
@@ -183,7 +200,7 @@ int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col
         CHEBFD_REQUIRE(h_col[k] >= 0 && h_col[k] < n, "column index %d at entry %lld out of range",
                        h_col[k], (long long)k);
     SellPlan p;
-    make_plan(n, h_rowptr, C, sigma, p);
+    make_plan(n, h_rowptr, h_order, C, sigma, p);
     const MatrixLayout L = matrix_layout(p, prec, C);
     if (bytes < L.total)
         CHEBFD_FAIL(CHEBFD_EWORKSPACE, "matrix buffer has %zu bytes, needs %zu", bytes, L.total);

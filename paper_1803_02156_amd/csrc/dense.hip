@@ -12,7 +12,7 @@
 //
 // MFMA: v_mfma_f64_16x16x4_f64 computes D(16x16) += A(16x4) B(4x16); lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
-// D[4 (l / 16) + r][l % 16] in its r-th accumulator (r = 0..3).
+// D[l / 16 + 4 r][l % 16] in its r-th accumulator (r = 0..3; measured on gfx950).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int prec_a, int
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int ra = wa + 16 * x + 4 * (lane / 16) + r;  // row of S (column of A)
+                const int ra = wa + 16 * x + lane / 16 + 4 * r;  // row of S (column of A)
                 const int cb = wb + 16 * y + lane % 16;            // column of S
                 double2 v;
                 v.x = acc[x][y][0][r] + acc[x][y][1][r];
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int prec_a, i
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + wi + 16 * x + 4 * (lane / 16) + r;
+                const int64_t i = i0 + wi + 16 * x + lane / 16 + 4 * r;
                 const int c = c0 + wc + 16 * y + lane % 16;
                 if (i < n && c < m2) {
                     double2 v;
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kJT) void jacobi_kernel(int m, double *A, int lda, 
     __syncthreads();
 
     int sweep = 0;
-    bool converged = false;
+    bool converged = m <= 1;
     for (sweep = 0; sweep < max_sweeps && !converged && m > 1; ++sweep) {
         for (int r = 0; r < me - 1; ++r) {
             // rotation parameters of this round
@@ -357,6 +357,14 @@ __global__ __launch_bounds__(kJT) void jacobi_kernel(int m, double *A, int lda, 
                 np.y = c * x.y - (sr * y.y + si * y.x);
                 nq.x = s * x.x + c * (er * y.x - ei * y.y);
                 nq.y = s * x.y + c * (er * y.y + ei * y.x);
+                // the pair's off-diagonal entries are annihilated by construction and
+                // its diagonal entries are real: store them exactly
+                if (cl == q) np = double2{0.0, 0.0};
+                if (cl == p) {
+                    nq = double2{0.0, 0.0};
+                    np.y = 0.0;
+                }
+                if (cl == q) nq.y = 0.0;
                 Ac[(int64_t)cl * lda + p] = np;
                 Ac[(int64_t)cl * lda + q] = nq;
             }

@@ -25,6 +25,12 @@ namespace {
 
 size_t al(size_t v) { return round_up(v, 256); }
 
+// Stopping tolerance of the Jacobi sweeps: off-diagonal Frobenius norm at most
+// 4 m u ||A||_F (u = 2^-53).  Once the rotations are at rounding level each of
+// the m(m-1) off-diagonal entries keeps a residue of order u ||A||, so a
+// tolerance independent of m would never be met.
+double jacobi_tol(int m) { return 4.0 * std::max(m, 1) * 0x1.0p-53; }
+
 int gram_splits(int64_t n) {
     return static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, n / 256)));
 }
@@ -172,7 +178,7 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
     hipStream_t s = static_cast<hipStream_t>(stream);
     int *info = static_cast<int *>(d_work);
     double *scratch = reinterpret_cast<double *>(static_cast<char *>(d_work) + 256);
-    if ((rc = launch_jacobi(m, d_a, lda, d_v, ldv, d_w, 40, 0x1.0p-52, info, scratch, s))) return rc;
+    if ((rc = launch_jacobi(m, d_a, lda, d_v, ldv, d_w, 40, jacobi_tol(m), info, scratch, s))) return rc;
     int h[2];
     CHEBFD_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, s));
     CHEBFD_HIP(hipStreamSynchronize(s));

@@ -1,0 +1,63 @@
+"""Row orders for lattice Hamiltonians, passed to ``chebfd_matrix_build(order=...)``.
+
+A fused Chebyshev step gathers, for every row, the block-vector rows of its
+lattice neighbours.  In the natural order (x fastest, then y, then z) the
+z-neighbours of a site are Nx Ny sites away, so on a large lattice they have
+left the cache before they are gathered again and the block vector U is read
+from memory about three times per step instead of once.  The orders here
+shorten those distances without changing the matrix (a symmetric permutation,
+like the sigma sort of SELL-C-sigma itself):
+
+* the lattice is cut into ``parts`` boxes (one per L2 domain: the step kernel
+  hands each of the eight XCDs of the device one contiguous eighth of the
+  rows), and
+* inside a box, sites are taken in slabs of ``slab`` y-lines; a slab is swept
+  z-plane by z-plane, so a site's z-neighbours are one slab plane
+  (box_x * slab sites) away instead of a whole lattice plane.
+
+Orbitals of a site stay consecutive (row = orbitals * site + orbital).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _split(dims, parts):
+    """Factor `parts` (a power of two) over the three extents, largest extent first."""
+    split = [1, 1, 1]
+    ext = list(dims)
+    p = parts
+    while p > 1:
+        k = int(np.argmax([e / s if e % (2 * s) == 0 else 0 for e, s in zip(ext, split)]))
+        if ext[k] % (2 * split[k]) != 0:
+            return None
+        split[k] *= 2
+        p //= 2
+    return tuple(split)
+
+
+def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int = 8, slab: int = 8):
+    """Row order (int32 permutation of 0..n-1, order[k] = original row placed k-th) for a
+    lattice with site index x + Nx (y + Ny z) and row orbitals * site + orbital.
+
+    Falls back to fewer boxes when the extents do not split evenly, and to slabs of
+    the full box width in y when ``slab`` does not divide it."""
+    dims = (int(Nx), int(Ny), int(Nz))
+    split = None
+    while parts >= 1 and split is None:
+        split = _split(dims, parts)
+        if split is None:
+            parts //= 2
+    px, py, pz = split
+    bx, by, bz = Nx // px, Ny // py, Nz // pz
+    sy = slab if (slab >= 1 and by % slab == 0) else by
+    x, y, z = np.meshgrid(np.arange(Nx), np.arange(Ny), np.arange(Nz), indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    site = x + Nx * (y + Ny * z)
+    box = (x // bx) + px * ((y // by) + py * (z // bz))
+    ly = y % by
+    # lexsort: the last key is the primary one
+    key = np.lexsort((x % bx, ly, z % bz, ly // sy, box))
+    sites = site[key]
+    rows = (orbitals * sites[:, None] + np.arange(orbitals)[None, :]).ravel()
+    return rows.astype(np.int32)

@@ -73,17 +73,17 @@ def test_matrix_query_validation(lib):
     n = len(rp) - 1
     sz = ctypes.c_size_t()
     p = rp.ctypes.data_as(ctypes.c_void_p)
-    assert lib.chebfd_matrix_query(n, p, 32, 256, 0, ctypes.byref(sz)) == 0
+    assert lib.chebfd_matrix_query(n, p, None, 32, 256, 0, ctypes.byref(sz)) == 0
     # 13 slots per row, no padding: col + c128 values, plus chunk tables and permutations
     assert sz.value >= n * 13 * (4 + 16) + 8 * n
-    assert lib.chebfd_matrix_query(n, p, 32, 256, 1, ctypes.byref(sz)) == 0
-    assert lib.chebfd_matrix_query(n, p, 24, 256, 0, ctypes.byref(sz)) == -1   # C not a power of 2
-    assert lib.chebfd_matrix_query(n, p, 32, 48, 0, ctypes.byref(sz)) == -1    # sigma not multiple of C
-    assert lib.chebfd_matrix_query(n, p, 32, 256, 2, ctypes.byref(sz)) == -1   # bad precision
-    assert lib.chebfd_matrix_query(0, p, 32, 256, 0, ctypes.byref(sz)) == -1   # empty matrix
+    assert lib.chebfd_matrix_query(n, p, None, 32, 256, 1, ctypes.byref(sz)) == 0
+    assert lib.chebfd_matrix_query(n, p, None, 24, 256, 0, ctypes.byref(sz)) == -1   # C not a power of 2
+    assert lib.chebfd_matrix_query(n, p, None, 32, 48, 0, ctypes.byref(sz)) == -1    # sigma not multiple of C
+    assert lib.chebfd_matrix_query(n, p, None, 32, 256, 2, ctypes.byref(sz)) == -1   # bad precision
+    assert lib.chebfd_matrix_query(0, p, None, 32, 256, 0, ctypes.byref(sz)) == -1   # empty matrix
     bad = rp.copy()
     bad[5] = bad[6] + 1
-    assert lib.chebfd_matrix_query(n, bad.ctypes.data_as(ctypes.c_void_p), 32, 256, 0, ctypes.byref(sz)) == -1
+    assert lib.chebfd_matrix_query(n, bad.ctypes.data_as(ctypes.c_void_p), None, 32, 256, 0, ctypes.byref(sz)) == -1
 
 
 def test_filter_rejects_null_handle(lib):

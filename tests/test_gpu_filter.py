@@ -201,3 +201,31 @@ def test_single_step_full_size_sampled_rows(P, prec):
         uu = EPS64 if prec == 0 else EPS32
         assert np.all(np.abs(Wg[i] - wn) <= 20 * uu * (scale + 1e-300))
         assert np.all(np.abs(Yg[i] - (Yh[i] + g * wn)) <= 20 * uu * (np.abs(Yh[i]) + abs(g) * scale))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("which", ["lattice", "random"])
+def test_filter_parity_with_row_order(P, prec, which):
+    """A caller row order (a symmetric permutation at ingest) changes only the
+    rounding order: parity with the oracle, which never sees the order."""
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    dims = (8, 8, 4)
+    H = topi_csr(*dims, m=1.0, W=1.5, seed=21)
+    n = len(H[0]) - 1
+    order = lattice_row_order(*dims) if which == "lattice" else \
+        np.random.default_rng(5).permutation(n).astype(np.int32)
+    n_s, n_b, n_p = 64, 32, 50
+    X = random_phase_block(n, n_s, 23)
+    M = P.chebfd_matrix_build(*H, prec=prec, order=order)
+    assert M.handle.identity_perm == 0
+    lo, hi = P.chebfd_bounds(M)
+    al, be, gam = P.chebfd_coefficients(lo, hi, -0.4, 0.3, n_p)
+    xb = P.chebfd_pack(M, _to_dev_colmajor(X), n_b)
+    eta, nu = P.chebfd_filter(M, al, be, gam, n_s, n_b, xb)
+    Y = P.chebfd_unpack(M, xb).cpu().numpy()
+    Yr, etar, nur = O.chebyshev_filter(H, al, be, gam, X, n_b)
+    u = EPS64 if prec == 0 else EPS32
+    s = np.max(np.abs(np.linalg.eigvalsh(csr_to_dense(*H)))) * al
+    bnd = _bound(n_p, 13, u, s) * np.sum(np.abs(gam))
+    assert np.max(np.abs(Y - Yr)) <= bnd
+    assert np.max(np.abs(nu.cpu().numpy()[1:] - nur[1:])) <= n * _bound(n_p, 13, u, s) * 4

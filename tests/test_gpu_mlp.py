@@ -73,7 +73,10 @@ def test_adam_matches_oracle_over_steps(P):
     for step in range(1, 4):
         g = torch.from_numpy(np.random.default_rng(step).standard_normal(theta.size).astype(np.float32)).cuda()
         P.chebfd_mlp_adam(p, g, m, v, step, lr=1e-2)
-        rt, rm, rv = OM.adam(rt, g.cpu().numpy().astype(np.float64), rm, rv, step, lr=1e-2)
+        # the kernel receives the hyper-parameters as float32: give the oracle the same values
+        f32 = lambda x: float(np.float32(x))  # noqa: E731
+        rt, rm, rv = OM.adam(rt, g.cpu().numpy().astype(np.float64), rm, rv, step, lr=f32(1e-2),
+                             beta1=f32(0.9), beta2=f32(0.999), eps=f32(1e-8))
         assert np.max(np.abs(p.cpu().numpy() - rt)) <= 1e-6 + 1e-5 * np.max(np.abs(rt))
         assert np.max(np.abs(v.cpu().numpy() - rv)) <= 1e-5 * np.max(rv)
 
@@ -101,7 +104,9 @@ def test_features_match_oracle(P, prec):
     f, cnt, al, be = P.chebfd_features(M, -0.3, 0.3, seed=11)
     lo, hi = O.gershgorin_bounds(H)
     ral, rbe = O.scale_factors(lo, hi)
-    assert abs(al - ral) < 1e-15 * ral and abs(be - rbe) < 1e-15
+    # bounds from the stored matrix values (c64 in mixed precision)
+    rel = 1e-15 if prec == 0 else 1e-6
+    assert abs(al - ral) < rel * ral and abs(be - rbe) < rel
     X = random_phase_block(n, 16, 11)
     _, eta, nu = O.chebyshev_filter(H, ral, rbe, np.zeros(129), X, 16)
     mu = np.real(np.sum(O.kpm_moments(eta, nu), axis=1)) / (n * 16)

@@ -1,0 +1,36 @@
+"""Lattice row orders for matrix ingest (host only)."""
+import numpy as np
+import pytest
+
+from paper_1803_02156_amd.ordering import lattice_row_order
+
+
+@pytest.mark.parametrize("dims,parts,slab", [((64, 64, 32), 8, 8), ((16, 16, 8), 8, 4), ((6, 5, 4), 8, 8),
+                                             ((12, 8, 10), 4, 2), ((3, 3, 3), 8, 8)])
+def test_is_a_permutation_with_orbitals_together(dims, parts, slab):
+    n = 4 * int(np.prod(dims))
+    o = lattice_row_order(*dims, parts=parts, slab=slab)
+    assert o.dtype == np.int32 and o.shape == (n,)
+    assert np.array_equal(np.sort(o), np.arange(n))
+    q = o.reshape(-1, 4)
+    assert np.all(q % 4 == np.arange(4)) and np.all(q // 4 == (q[:, :1] // 4))
+
+
+def test_neighbour_distances_shrink():
+    Nx, Ny, Nz = 64, 64, 32
+    o = lattice_row_order(Nx, Ny, Nz)
+    pos = np.empty(o.size, dtype=np.int64)
+    pos[o] = np.arange(o.size)
+    s = np.arange(Nx * Ny * Nz)
+    x, y, z = s % Nx, (s // Nx) % Ny, s // (Nx * Ny)
+    zn = x + Nx * (y + Ny * ((z + 1) % Nz))
+    d_new = np.abs(pos[4 * zn] - pos[4 * s])
+    d_old = 4 * Nx * Ny
+    # within a box and slab the z-neighbour is one slab plane away (box_x * 8 sites)
+    assert np.median(d_new) <= 4 * 32 * 8 < d_old
+    # the boxes are contiguous eighths
+    box_rows = o.size // 8
+    sites_of = o.reshape(8, box_rows)[:, ::4] // 4
+    for b in range(8):
+        xs, ys, zs = sites_of[b] % Nx, (sites_of[b] // Nx) % Ny, sites_of[b] // (Nx * Ny)
+        assert np.ptp(xs) < 64 and (np.ptp(xs) + 1) * (np.ptp(ys) + 1) * (np.ptp(zs) + 1) == box_rows // 4
