@@ -230,7 +230,7 @@ int chebfd_update(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec_a
  * cyclic Jacobi rotations in one workgroup: d_w receives the eigenvalues in
  * ascending order, d_v (ldv) the eigenvectors; d_a (lda) is overwritten.
  * Synchronises `stream`; CHEBFD_ENUMERIC if 40 sweeps do not reduce the
- * off-diagonal Frobenius norm below 2^-52 of the matrix's.
+ * off-diagonal Frobenius norm below 4 m 2^-53 of the matrix's.
  */
 int chebfd_heev_query(int32_t m, size_t *work_bytes);
 int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, double *d_w,
@@ -248,6 +248,14 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
  * pairs repeats and every pair in the interval is converged or spurious
  * (status CHEBFD_OK), after max_iter iterations (CHEBFD_NOT_CONVERGED), or when
  * more than 3/4 n_s Ritz values fall in the interval (CHEBFD_SUBSPACE_SMALL).
+ *
+ * Mixed precision (p->prec MIXED): the c64 basis bounds the residuals below by
+ * about 2^-24 |lambda - theta|.  The iteration therefore runs in two stages:
+ * c64 until the interval's pairs reach max(tol, 16 2^-24 max|lam_lo|,|lam_hi|)
+ * or their residuals stop halving, then FP64 (filter with H64, blocks of
+ * n_b / 2) on the Ritz vectors closest to the interval, the in-interval ones
+ * first, at most n_s / 2 of them (kept in the c64 basis buffers), until the
+ * convergence rule holds with tol.  Both stages count towards max_iter.
  *
  * H is the filter's matrix (precision p->prec); H64 an FP64 copy of the same
  * matrix (same n, C, sigma) for the Rayleigh-Ritz products and residuals (may

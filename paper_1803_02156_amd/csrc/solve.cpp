@@ -51,6 +51,12 @@ int solve_layout(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     if (rc) return rc;
     if ((rc = chebfd_filter_query(H64, p->n_b, &f2))) return rc;
     L->fwork_bytes = std::max(f1, f2);
+    if (p->prec != CHEBFD_PREC_FP64 && p->n_b > 1) {
+        // the FP64 stage of a mixed run filters with n_b / 2
+        size_t f3 = 0;
+        if ((rc = chebfd_filter_query(H64, p->n_b / 2, &f3))) return rc;
+        L->fwork_bytes = std::max(L->fwork_bytes, f3);
+    }
     L->gpart_bytes = gram_part_bytes(p->n_s, p->n_s, gram_splits(H->n));
     L->rgrid = resid_grid(H->n);
     L->rpart_bytes = (size_t)2 * nb * L->rgrid * 8;
@@ -245,18 +251,33 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     for (auto &t : ev)
         for (auto &e : t.e) CHEBFD_HIP(hipEventCreate(&e));
     double t_phase[4] = {0, 0, 0, 0};
-    const double tau = tau_for(prec);
     std::vector<double> hw(ns), hth(ns), hrr(2 * nb), hres(ns), hnrm(ns);
     std::vector<double> heta, hnu;
     double count_est = 0.0;
-    int status = CHEBFD_NOT_CONVERGED, it = 0, prev = -1, k2 = 0;
+    int status = CHEBFD_NOT_CONVERGED, it = 0, k2 = 0;
     double fbytes = 0.0;
-    void *X = D(L.x), *Q = D(L.q);
 
-    // one SVQB step: A (m columns) -> B (k kept columns); returns k
-    auto svqb = [&](void *A, int m, void *B, int *k) -> int {
+    // The working set of one stage of the iteration.  Stage 1 runs in the
+    // caller's precision on all n_s vectors.  In mixed precision the c64
+    // storage of the basis puts a floor of about 2^-24 |lambda - theta| under
+    // the residuals; stage 2 then continues in FP64 (matrix H64) from the
+    // Ritz vectors nearest the interval, at most n_s / 2 of them in blocks of
+    // n_b / 2, held in the c64 basis buffers (same bytes).
+    struct Stage {
+        const chebfd_matrix *H;
+        int prec, ns, nb;
+        void *X, *Q, *U, *W;
+        double tol;
+    };
+    Stage S1{H, prec, ns, nb, D(L.x), D(L.q), D(L.u), D(L.w), p->tol};
+    const double hmax = std::max(std::fabs(lo), std::fabs(hi));
+    if (prec != CHEBFD_PREC_FP64) S1.tol = std::max(p->tol, 16.0 * 0x1.0p-24 * hmax);
+
+    // one SVQB step on the stage's basis: A (m columns) -> B (k kept columns)
+    auto svqb = [&](const Stage &g, void *A, int m, void *B, int *k) -> int {
         int r;
-        if ((r = launch_gram(A, prec, nb, A, prec, nb, n, m, m, DD(L.gpart), gram_splits(n), DD(L.S), ns, s)))
+        if ((r = launch_gram(A, g.prec, g.nb, A, g.prec, g.nb, n, m, m, DD(L.gpart), gram_splits(n), DD(L.S), ns,
+                             s)))
             return r;
         if ((r = launch_svqb_scale(m, DD(L.S), ns, DD(L.d), s))) return r;
         if ((r = chebfd_heev(m, DD(L.S), ns, DD(L.V), ns, DD(L.wv), D(L.jwork), L.jwork_bytes, stream, nullptr)))
@@ -265,136 +286,203 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
         CHEBFD_HIP(hipStreamSynchronize(s));
         const double wmax = hw[m - 1];
         if (!(wmax > 0.0) || !std::isfinite(wmax)) CHEBFD_FAIL(CHEBFD_ENUMERIC, "SVQB: non-positive Gram matrix");
+        const double tau = tau_for(g.prec);
         int kk = 0;
         for (int i = 0; i < m; ++i) kk += hw[i] > tau * wmax ? 1 : 0;
         if ((r = launch_svqb_transform(m, kk, m - kk, DD(L.d), DD(L.V), ns, DD(L.wv), DD(L.T), ns, s))) return r;
-        if ((r = launch_update(A, prec, nb, DD(L.T), ns, B, prec, nb, n, m, kk, s))) return r;
+        if ((r = launch_update(A, g.prec, g.nb, DD(L.T), ns, B, g.prec, g.nb, n, m, kk, s))) return r;
         *k = kk;
         return CHEBFD_OK;
     };
 
-    for (it = 1; it <= p->max_iter; ++it) {
-        // --- filter (Alg. 2 over blocks, Alg. 1 per block) ---
-        CHEBFD_HIP(hipEventRecord(ev[0].e[0], s));
-        double *d_eta = it == 1 ? DD(L.eta) : nullptr, *d_nu = it == 1 ? DD(L.nu) : nullptr;
-        if ((rc = chebfd_filter(H, alpha, beta, gamma.data(), p->n_p, ns, nb, prec, X, D(L.u), D(L.w), d_eta,
-                                d_nu, D(L.fwork), L.fwork_bytes, stream)))
-            return rc;
-        CHEBFD_HIP(hipEventRecord(ev[0].e[1], s));
-        fbytes += (double)(ns / nb) * ((double)(p->n_p - 2) * (double)(H->nnz * (sw + 4) + 5 * n * nb * sw) +
-                                       2.0 * (double)(H->nnz * (sw + 4)) + 6.0 * n * nb * sw);
-        if (it == 1) {
-            // moments -> eigenvalue count estimate (trace of the damped window polynomial)
-            heta.resize((size_t)2 * (p->n_p + 1) * ns);
-            hnu.resize((size_t)(p->n_p + 1) * ns);
-            CHEBFD_HIP(hipMemcpyAsync(heta.data(), DD(L.eta), sizeof(double) * heta.size(), hipMemcpyDeviceToHost, s));
-            CHEBFD_HIP(hipMemcpyAsync(hnu.data(), DD(L.nu), sizeof(double) * hnu.size(), hipMemcpyDeviceToHost, s));
-            CHEBFD_HIP(hipStreamSynchronize(s));
-            std::vector<double> se(p->n_p + 1, 0.0), sn(p->n_p + 1, 0.0);
-            for (int q = 1; q <= p->n_p; ++q)
-                for (int j = 0; j < ns; ++j) {
-                    se[q] += heta[2 * ((size_t)q * ns + j)];
-                    sn[q] += hnu[(size_t)q * ns + j];
+    // Iterations of one stage until its convergence rule holds or max_iter is
+    // reached.  prev: in-window converged count the first test compares with.
+    // On return the stage's X holds the last kept basis, S its Ritz vectors
+    // (coefficients), hth / hres the k2 Ritz values and residuals.
+    auto run_stage = [&](Stage &g, int prev, bool stage1, bool *stagnated) -> int {
+        const size_t swg = vec_elem_bytes(g.prec);
+        double prev_max = INFINITY;
+        int prev_inwin = -1;
+        *stagnated = false;
+        for (++it; it <= p->max_iter; ++it) {
+            // --- filter (Alg. 2 over blocks, Alg. 1 per block) ---
+            CHEBFD_HIP(hipEventRecord(ev[0].e[0], s));
+            const bool moments = stage1 && it == 1;
+            double *d_eta = moments ? DD(L.eta) : nullptr, *d_nu = moments ? DD(L.nu) : nullptr;
+            int r;
+            if ((r = chebfd_filter(g.H, alpha, beta, gamma.data(), p->n_p, g.ns, g.nb, g.prec, g.X, g.U, g.W, d_eta,
+                                   d_nu, D(L.fwork), L.fwork_bytes, stream)))
+                return r;
+            CHEBFD_HIP(hipEventRecord(ev[0].e[1], s));
+            fbytes += (double)(g.ns / g.nb) *
+                      ((double)(p->n_p - 2) * (double)(g.H->nnz * (swg + 4) + 5 * n * g.nb * swg) +
+                       2.0 * (double)(g.H->nnz * (swg + 4)) + 6.0 * n * g.nb * swg);
+            if (moments) {
+                // moments -> eigenvalue count estimate (trace of the damped window polynomial)
+                heta.resize((size_t)2 * (p->n_p + 1) * ns);
+                hnu.resize((size_t)(p->n_p + 1) * ns);
+                CHEBFD_HIP(hipMemcpyAsync(heta.data(), DD(L.eta), sizeof(double) * heta.size(), hipMemcpyDeviceToHost, s));
+                CHEBFD_HIP(hipMemcpyAsync(hnu.data(), DD(L.nu), sizeof(double) * hnu.size(), hipMemcpyDeviceToHost, s));
+                CHEBFD_HIP(hipStreamSynchronize(s));
+                std::vector<double> se(p->n_p + 1, 0.0), sn(p->n_p + 1, 0.0);
+                for (int q = 1; q <= p->n_p; ++q)
+                    for (int j = 0; j < ns; ++j) {
+                        se[q] += heta[2 * ((size_t)q * ns + j)];
+                        sn[q] += hnu[(size_t)q * ns + j];
+                    }
+                const double mu0 = sn[1], mu1 = se[1];
+                double acc = gamma2[0] * mu0 + gamma2[1] * mu1;
+                for (int k = 1; k < p->n_p; ++k)
+                    acc += gamma2[2 * k] * (2.0 * sn[k + 1] - mu0) + gamma2[2 * k + 1] * (2.0 * se[k + 1] - mu1);
+                count_est = acc / ns;   // n * sum g c mu~ with mu~ = mu / (n R)
+            }
+
+            // --- SVQB twice ---
+            CHEBFD_HIP(hipEventRecord(ev[1].e[0], s));
+            int k1 = 0;
+            if ((r = svqb(g, g.X, g.ns, g.Q, &k1))) return r;
+            if ((r = svqb(g, g.Q, k1, g.X, &k2))) return r;
+            CHEBFD_HIP(hipEventRecord(ev[1].e[1], s));
+
+            // --- Rayleigh-Ritz on the k2 kept directions (FP64 products) ---
+            CHEBFD_HIP(hipEventRecord(ev[2].e[0], s));
+            const int kb = (k2 + g.nb - 1) / g.nb;
+            for (int b = 0; b < kb; ++b) {
+                const void *Xb = static_cast<const char *>(g.X) + (size_t)b * n * g.nb * swg;
+                const void *X64 = Xb;
+                if (g.prec != CHEBFD_PREC_FP64) {
+                    if ((r = launch_convert(Xb, g.prec, D(L.b64), CHEBFD_PREC_FP64, n * g.nb, s))) return r;
+                    X64 = D(L.b64);
                 }
-            const double mu0 = sn[1], mu1 = se[1];
-            double acc = gamma2[0] * mu0 + gamma2[1] * mu1;
-            for (int k = 1; k < p->n_p; ++k)
-                acc += gamma2[2 * k] * (2.0 * sn[k + 1] - mu0) + gamma2[2 * k + 1] * (2.0 * se[k + 1] - mu1);
-            count_est = acc / ns;   // n * sum g c mu~ with mu~ = mu / (n R)
-        }
-
-        // --- SVQB twice ---
-        CHEBFD_HIP(hipEventRecord(ev[1].e[0], s));
-        int k1 = 0;
-        if ((rc = svqb(X, ns, Q, &k1))) return rc;
-        if ((rc = svqb(Q, k1, X, &k2))) return rc;
-        CHEBFD_HIP(hipEventRecord(ev[1].e[1], s));
-
-        // --- Rayleigh-Ritz on the k2 kept directions (FP64 products) ---
-        CHEBFD_HIP(hipEventRecord(ev[2].e[0], s));
-        const int kb = (k2 + nb - 1) / nb;
-        for (int b = 0; b < kb; ++b) {
-            const void *Xb = static_cast<const char *>(X) + (size_t)b * n * nb * sw;
-            const void *X64 = Xb;
-            if (prec != CHEBFD_PREC_FP64) {
-                if ((rc = launch_convert(Xb, prec, D(L.b64), CHEBFD_PREC_FP64, n * nb, s))) return rc;
-                X64 = D(L.b64);
+                if ((r = chebfd_spmmv(H64, 1.0, 0.0, g.nb, CHEBFD_PREC_FP64, X64, D(L.t64), D(L.fwork), L.fwork_bytes,
+                                      stream)))
+                    return r;
+                const int cols = std::min(g.nb, k2 - b * g.nb);
+                if ((r = launch_gram(g.X, g.prec, g.nb, D(L.t64), CHEBFD_PREC_FP64, g.nb, n, k2, cols, DD(L.gpart),
+                                     gram_splits(n), DD(L.G) + 2 * (size_t)b * g.nb * ns, ns, s)))
+                    return r;
             }
-            if ((rc = chebfd_spmmv(H64, 1.0, 0.0, nb, CHEBFD_PREC_FP64, X64, D(L.t64), D(L.fwork), L.fwork_bytes,
-                                   stream)))
-                return rc;
-            const int cols = std::min(nb, k2 - b * nb);
-            if ((rc = launch_gram(X, prec, nb, D(L.t64), CHEBFD_PREC_FP64, nb, n, k2, cols, DD(L.gpart),
-                                  gram_splits(n), DD(L.G) + 2 * (size_t)b * nb * ns, ns, s)))
-                return rc;
-        }
-        if ((rc = launch_hermitise(k2, DD(L.G), ns, s))) return rc;
-        if ((rc = chebfd_heev(k2, DD(L.G), ns, DD(L.S), ns, DD(L.theta), D(L.jwork), L.jwork_bytes, stream,
-                              nullptr)))
-            return rc;
-        CHEBFD_HIP(hipEventRecord(ev[2].e[1], s));
+            if ((r = launch_hermitise(k2, DD(L.G), ns, s))) return r;
+            if ((r = chebfd_heev(k2, DD(L.G), ns, DD(L.S), ns, DD(L.theta), D(L.jwork), L.jwork_bytes, stream,
+                                 nullptr)))
+                return r;
+            CHEBFD_HIP(hipEventRecord(ev[2].e[1], s));
 
-        // --- residuals ||H z - theta z|| / ||z|| with z = X S in FP64 ---
-        CHEBFD_HIP(hipEventRecord(ev[3].e[0], s));
-        for (int b = 0; b < kb; ++b) {
-            const int cols = std::min(nb, k2 - b * nb);
-            if ((rc = launch_update(X, prec, nb, DD(L.S) + 2 * (size_t)b * nb * ns, ns, D(L.z64), CHEBFD_PREC_FP64,
-                                    nb, n, k2, cols, s)))
-                return rc;
-            if ((rc = chebfd_spmmv(H64, 1.0, 0.0, nb, CHEBFD_PREC_FP64, D(L.z64), D(L.t64), D(L.fwork),
-                                   L.fwork_bytes, stream)))
-                return rc;
-            if ((rc = launch_resid(D(L.t64), D(L.z64), CHEBFD_PREC_FP64, n, nb, DD(L.theta) + (size_t)b * nb,
-                                   DD(L.rpart), L.rgrid, DD(L.rr), s)))
-                return rc;
-            CHEBFD_HIP(hipMemcpyAsync(hrr.data(), DD(L.rr), sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s));
+            // --- residuals ||H z - theta z|| / ||z|| with z = X S in FP64 ---
+            CHEBFD_HIP(hipEventRecord(ev[3].e[0], s));
+            for (int b = 0; b < kb; ++b) {
+                const int cols = std::min(g.nb, k2 - b * g.nb);
+                if ((r = launch_update(g.X, g.prec, g.nb, DD(L.S) + 2 * (size_t)b * g.nb * ns, ns, D(L.z64),
+                                       CHEBFD_PREC_FP64, g.nb, n, k2, cols, s)))
+                    return r;
+                if ((r = chebfd_spmmv(H64, 1.0, 0.0, g.nb, CHEBFD_PREC_FP64, D(L.z64), D(L.t64), D(L.fwork),
+                                      L.fwork_bytes, stream)))
+                    return r;
+                if ((r = launch_resid(D(L.t64), D(L.z64), CHEBFD_PREC_FP64, n, g.nb, DD(L.theta) + (size_t)b * g.nb,
+                                      DD(L.rpart), L.rgrid, DD(L.rr), s)))
+                    return r;
+                CHEBFD_HIP(hipMemcpyAsync(hrr.data(), DD(L.rr), sizeof(double) * 2 * g.nb, hipMemcpyDeviceToHost, s));
+                CHEBFD_HIP(hipStreamSynchronize(s));
+                for (int c = 0; c < cols; ++c) {
+                    hres[b * g.nb + c] = std::sqrt(hrr[2 * c]);
+                    hnrm[b * g.nb + c] = std::sqrt(hrr[2 * c + 1]);
+                }
+            }
+            CHEBFD_HIP(hipMemcpyAsync(hth.data(), DD(L.theta), sizeof(double) * k2, hipMemcpyDeviceToHost, s));
+            CHEBFD_HIP(hipEventRecord(ev[3].e[1], s));
             CHEBFD_HIP(hipStreamSynchronize(s));
-            for (int c = 0; c < cols; ++c) {
-                hres[b * nb + c] = std::sqrt(hrr[2 * c]);
-                hnrm[b * nb + c] = std::sqrt(hrr[2 * c + 1]);
+            for (int q = 0; q < 4; ++q) {
+                float ms = 0.0f;
+                CHEBFD_HIP(hipEventElapsedTime(&ms, ev[q].e[0], ev[q].e[1]));
+                t_phase[q] += ms * 1e-3;
             }
-        }
-        CHEBFD_HIP(hipMemcpyAsync(hth.data(), DD(L.theta), sizeof(double) * k2, hipMemcpyDeviceToHost, s));
-        CHEBFD_HIP(hipEventRecord(ev[3].e[1], s));
-        CHEBFD_HIP(hipStreamSynchronize(s));
-        for (int q = 0; q < 4; ++q) {
-            float ms = 0.0f;
-            CHEBFD_HIP(hipEventElapsedTime(&ms, ev[q].e[0], ev[q].e[1]));
-            t_phase[q] += ms * 1e-3;
-        }
-        for (int c = 0; c < k2; ++c) {
-            hres[c] = hnrm[c] > 0.0 ? hres[c] / hnrm[c] : INFINITY;
-            if (!std::isfinite(hth[c])) CHEBFD_FAIL(CHEBFD_ENUMERIC, "non-finite Ritz value");
-        }
+            for (int c = 0; c < k2; ++c) {
+                hres[c] = hnrm[c] > 0.0 ? hres[c] / hnrm[c] : INFINITY;
+                if (!std::isfinite(hth[c])) CHEBFD_FAIL(CHEBFD_ENUMERIC, "non-finite Ritz value");
+            }
 
-        // --- convergence test ---
-        int inwin = 0, conv = 0;
-        bool all_ok = true;
-        for (int c = 0; c < k2; ++c) {
-            if (hth[c] < p->lam_L || hth[c] > p->lam_R) continue;
-            ++inwin;
-            const bool cv = hres[c] <= p->tol;
-            const bool spur = hres[c] > 0.5 * (p->lam_R - p->lam_L);
-            conv += cv ? 1 : 0;
-            all_ok = all_ok && (cv || spur);
-        }
-        if (inwin > 0.75 * ns) {
-            status = CHEBFD_SUBSPACE_SMALL;
-            break;
-        }
-        if (conv == prev && all_ok) {
-            status = CHEBFD_OK;
-            break;
-        }
-        prev = conv;
-        if (it == p->max_iter) break;
+            // --- convergence test ---
+            int inwin = 0, conv = 0;
+            bool all_ok = true;
+            double worst = 0.0;
+            for (int c = 0; c < k2; ++c) {
+                if (hth[c] < p->lam_L || hth[c] > p->lam_R) continue;
+                ++inwin;
+                const bool cv = hres[c] <= g.tol;
+                const bool spur = hres[c] > 0.5 * (p->lam_R - p->lam_L);
+                conv += cv ? 1 : 0;
+                all_ok = all_ok && (cv || spur);
+                if (!spur) worst = std::max(worst, hres[c]);
+            }
+            if (stage1 && inwin > 0.75 * g.ns) return CHEBFD_SUBSPACE_SMALL;
+            if (conv == prev && all_ok) return CHEBFD_OK;
+            // stage 1 of a mixed run also ends when the residuals stop falling (storage floor)
+            if (stage1 && g.prec != CHEBFD_PREC_FP64 && inwin > 0 && inwin == prev_inwin && conv == prev &&
+                worst > 0.5 * prev_max) {
+                *stagnated = true;
+                return CHEBFD_OK;
+            }
+            prev = conv;
+            prev_max = worst;
+            prev_inwin = inwin;
+            if (it == p->max_iter) break;
 
-        // --- restart: Ritz vectors, then fresh random phases for dropped directions ---
-        if ((rc = launch_update(X, prec, nb, DD(L.S), ns, Q, prec, nb, n, k2, k2, s))) return rc;
-        if ((rc = launch_random_phase(Q, prec, n, nb, k2, ns, p->seed, (uint64_t)it * ns, perm, s))) return rc;
-        std::swap(X, Q);
+            // --- restart: Ritz vectors, then fresh random phases for dropped directions ---
+            if ((r = launch_update(g.X, g.prec, g.nb, DD(L.S), ns, g.Q, g.prec, g.nb, n, k2, k2, s))) return r;
+            if ((r = launch_random_phase(g.Q, g.prec, n, g.nb, k2, g.ns, p->seed, (uint64_t)it * ns, perm, s)))
+                return r;
+            std::swap(g.X, g.Q);
+        }
+        return CHEBFD_NOT_CONVERGED;
+    };
+
+    bool stagnated = false;
+    Stage *fin = &S1;
+    status = run_stage(S1, -1, true, &stagnated);
+    if (status < 0) return status;
+    Stage S2{H64, CHEBFD_PREC_FP64, 0, std::max(1, nb / 2), S1.Q, S1.X, D(L.b64), D(L.t64), p->tol};
+    if (prec != CHEBFD_PREC_FP64 && status == CHEBFD_OK && it < p->max_iter) {
+        // --- stage 2 (mixed precision): FP64 iteration on the Ritz vectors nearest the interval ---
+        std::vector<int> pick;
+        for (int c = 0; c < k2; ++c)
+            if (hth[c] >= p->lam_L && hth[c] <= p->lam_R) pick.push_back(c);
+        const int inwin = static_cast<int>(pick.size());
+        const int ns2_max = ns / 2 / S2.nb * S2.nb;
+        int ns2 = std::max(inwin + 2, (4 * inwin + 2) / 3 + 1);
+        ns2 = std::min(ns2_max, (ns2 + S2.nb - 1) / S2.nb * S2.nb);
+        if (inwin > 0 && ns2 >= inwin && ns2 <= k2) {
+            const double mid = 0.5 * (p->lam_L + p->lam_R);
+            std::vector<int> rest;
+            for (int c = 0; c < k2; ++c)
+                if (!(hth[c] >= p->lam_L && hth[c] <= p->lam_R)) rest.push_back(c);
+            std::stable_sort(rest.begin(), rest.end(),
+                             [&](int a, int b) { return std::fabs(hth[a] - mid) < std::fabs(hth[b] - mid); });
+            for (int c : rest)
+                if ((int)pick.size() < ns2) pick.push_back(c);
+            S2.ns = ns2;
+            CHEBFD_HIP(hipMemcpyAsync(D(L.order), pick.data(), sizeof(int) * ns2, hipMemcpyHostToDevice, s));
+            if ((rc = launch_permute_columns(k2, ns2, DD(L.S), ns, static_cast<const int *>(D(L.order)), DD(L.T), ns,
+                                             s)))
+                return rc;
+            // FP64 Ritz vectors into the idle basis buffer (X of stage 2), block width n_b / 2
+            if ((rc = launch_update(S1.X, prec, nb, DD(L.T), ns, S1.Q, CHEBFD_PREC_FP64, S2.nb, n, k2, ns2, s)))
+                return rc;
+            S2.X = S1.Q;
+            S2.Q = S1.X;
+            CHEBFD_HIP(hipStreamSynchronize(s));
+            bool dummy;
+            status = run_stage(S2, inwin, false, &dummy);
+            if (status < 0) return status;
+            fin = &S2;
+        } else if (stagnated || S1.tol > p->tol) {
+            status = CHEBFD_NOT_CONVERGED;
+        }
+    } else if (prec != CHEBFD_PREC_FP64 && status == CHEBFD_OK) {
+        status = CHEBFD_NOT_CONVERGED;   // no iteration left for the FP64 stage
     }
     if (it > p->max_iter) it = p->max_iter;
+    void *X = fin->X;
+    const int fprec = fin->prec, fnb = fin->nb;
 
     // output order: converged pairs inside the interval first, then the rest
     std::vector<int> order;
@@ -413,25 +501,26 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
         if ((rc = launch_permute_columns(k2, k2, DD(L.S), ns, static_cast<const int *>(D(L.order)), DD(L.T), ns, s)))
             return rc;
         CHEBFD_HIP(hipMemsetAsync(d_Z, 0, sizeof(double) * 2 * (size_t)n * ns, s));
-        const int kb = (k2 + nb - 1) / nb;
+        const int kb = (k2 + fnb - 1) / fnb;
         for (int b = 0; b < kb; ++b) {
-            const int cols = std::min(nb, k2 - b * nb);
-            if ((rc = launch_update(X, prec, nb, DD(L.T) + 2 * (size_t)b * nb * ns, ns, D(L.z64), CHEBFD_PREC_FP64,
-                                    nb, n, k2, cols, s)))
+            const int cols = std::min(fnb, k2 - b * fnb);
+            if ((rc = launch_update(X, fprec, fnb, DD(L.T) + 2 * (size_t)b * fnb * ns, ns, D(L.z64), CHEBFD_PREC_FP64,
+                                    fnb, n, k2, cols, s)))
                 return rc;
-            if ((rc = launch_fix_phases(D(L.z64), CHEBFD_PREC_FP64, n, nb, cols, DD(L.phase), s))) return rc;
-            if ((rc = launch_pack(perm, n, nb, nb, CHEBFD_PREC_FP64, D(L.z64),
-                                  static_cast<char *>(d_Z) + (size_t)b * nb * n * 16, true, s)))
+            if ((rc = launch_fix_phases(D(L.z64), CHEBFD_PREC_FP64, n, fnb, cols, DD(L.phase), s))) return rc;
+            // columns b*fnb .. (b+1)*fnb-1 of the column-major output (fnb divides n_s)
+            if ((rc = launch_pack(perm, n, fnb, fnb, CHEBFD_PREC_FP64, D(L.z64),
+                                  static_cast<char *>(d_Z) + (size_t)b * fnb * n * 16, true, s)))
                 return rc;
         }
-        if (k2 % nb) {
-            // the last block's columns past k2 received the update's zeros; re-zero to be explicit
-            const int b = k2 / nb;
-            const size_t c0 = (size_t)k2;
-            CHEBFD_HIP(hipMemsetAsync(static_cast<char *>(d_Z) + c0 * n * 16, 0, ((size_t)(b + 1) * nb - c0) * n * 16, s));
+        if (k2 % fnb) {
+            // the last block's columns past k2 hold stale z64 data: zero them
+            const size_t c0 = (size_t)k2, c1 = (size_t)(k2 / fnb + 1) * fnb;
+            CHEBFD_HIP(hipMemsetAsync(static_cast<char *>(d_Z) + c0 * n * 16, 0, (c1 - c0) * n * 16, s));
         }
         CHEBFD_HIP(hipStreamSynchronize(s));
     }
+
     if (st) {
         st->iterations = it;
         st->n_found = nf;

@@ -174,7 +174,7 @@ def test_solve_small_configuration_fp64_and_mixed(P):
     assert np.max(r64.resid[:12]) <= 1e-9
     M32 = P.chebfd_matrix_build(*H, prec=1)
     r32 = P.chebfd_solve(M32, M64, -0.05, 0.05, 32, 200, 32, tol=1e-7, seed=43)
-    assert r32.status == 0 and r32.n_found == 12
+    assert r32.status == 0 and r32.n_found == 12, (r32, r32.resid[:16], r32.theta[:16])
     assert np.max(r32.resid[:12]) <= 1e-7
     # eigenvalue error is quadratic in the residual: far below the residual itself
     assert np.max(np.abs(r32.theta[:12] - orc.theta[:12])) < 1e-10
@@ -222,3 +222,19 @@ def test_kpm_moments_match_oracle(P, prec, R, n_steps):
     assert abs(mu[0] - 1.0) < 10 * u
     assert np.max(np.abs(mu - ref)) < 50 * u * n_steps
     assert np.all(np.abs(mu) <= 1.0 + 100 * u * n_steps)      # |T_m| <= 1 on [-1, 1]
+
+
+def test_solve_mixed_matches_fp64_on_disordered_lattice(P):
+    H = topi_csr(6, 6, 4, m=1.0, W=1.0, seed=1001)
+    A = csr_to_dense(*H)
+    e = np.linalg.eigvalsh(A)
+    ref = e[(e >= -0.35) & (e <= 0.35)]
+    M64 = P.chebfd_matrix_build(*H, prec=0)
+    M32 = P.chebfd_matrix_build(*H, prec=1)
+    r = P.chebfd_solve(M32, M64, -0.35, 0.35, 32, 200, 32, tol=1e-7, seed=43)
+    assert r.status == 0 and r.n_found == len(ref), (r, r.resid[:12])
+    nf = r.n_found
+    assert np.max(r.resid[:nf]) <= 1e-7
+    assert np.max(np.abs(np.sort(r.theta[:nf]) - ref)) < 1e-12
+    Z = r.Z.cpu().numpy()[:, :nf]
+    assert np.max(np.linalg.norm(A @ Z - Z * r.theta[None, :nf], axis=0) / np.linalg.norm(Z, axis=0)) <= 1e-7
