@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--solve-count", type=float, default=100.0,
                     help="eigenvalue count the symmetric search interval is sized for")
     ap.add_argument("--op-launches", type=int, default=200, help="launches of the fused step timed alone")
+    ap.add_argument("--order", choices=("lattice", "natural"), default="lattice",
+                    help="row order at ingest: lattice boxes/slabs (one box per XCD) or the natural order")
     return ap.parse_args()
 
 
@@ -60,10 +62,11 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def counter_traffic(prec: int, n_b: int, lattice: str):
+def counter_traffic(prec: int, n_b: int, lattice: str, order: str):
     """HBM bytes per fused-step launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, if it was taken on the current kernel source; else None."""
-    name = f"traffic_cheb_lds_step_topi{lattice.replace('x', '-')}_{'fp64' if prec == 0 else 'mixed'}_nb{n_b}.json"
+    name = (f"traffic_cheb_lds_step_topi{lattice.replace('x', '-')}_{'fp64' if prec == 0 else 'mixed'}"
+            f"_nb{n_b}_{order}.json")
     path = os.path.join(HERE, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -74,42 +77,43 @@ def counter_traffic(prec: int, n_b: int, lattice: str):
     return t["hbm_bytes_per_launch"]
 
 
-def interval_for_count(P, M, target, seed=7):
+def interval_for_count(P, M, target, seed=7, n_steps=1024, R=16):
     """Half width delta of the symmetric interval [-delta, delta] whose KPM count
-    estimate (256 moments, 16 random-phase vectors) is closest to `target`."""
+    estimate (2 n_steps moments of R random-phase vectors, Jackson-damped window)
+    is closest to `target`: the moments once on the device, the bisection on them."""
     lo_b, hi_b = P.chebfd_bounds(M)
-    half = max(abs(lo_b), abs(hi_b))
-    a, b = 1e-4 * half, 0.5 * half
-    cache = {}
+    al, be, _ = P.chebfd_coefficients(lo_b, hi_b, -1e-3, 1e-3, 1)
+    mu = P.chebfd_kpm_moments(M, al, be, n_steps, R, seed)
 
     def count(d):
-        if d not in cache:
-            cache[d] = P.chebfd_features(M, -d, d, seed)[1]
-        return cache[d]
-    for _ in range(40):
+        _, _, gc = P.chebfd_coefficients(lo_b, hi_b, -d, d, 2 * n_steps - 1)
+        return float(M.n * np.dot(gc, mu))
+    half = max(abs(lo_b), abs(hi_b))
+    a, b = 1e-4 * half, 0.5 * half
+    for _ in range(60):
         mid = 0.5 * (a + b)
         if count(mid) < target:
             a = mid
         else:
             b = mid
-        if b - a < 1e-4 * b:
+        if b - a < 1e-6 * b:
             break
     return 0.5 * (a + b), count(0.5 * (a + b))
 
 
-def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target):
+def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target, order):
     """Full ChebFD runs (filter, SVQB, Rayleigh-Ritz, residuals, restarts) in FP64 and
     mixed precision on the same matrix and interval; wall time from the first launch
     to the synchronised end, matrix build excluded."""
     import torch
-    M64 = P.chebfd_matrix_build(*H, prec=0)
+    M64 = P.chebfd_matrix_build(*H, prec=0, order=order)
     delta, cnt = interval_for_count(P, M64, target)
     out = {"workload": f"Topi-{Nx}-{Ny}-{Nz} (W={W}), interval [-{delta:.6g}, {delta:.6g}] "
-                       f"(KPM count estimate {cnt:.1f}), n_s={n_s}, n_b={n_b}, n_p={n_p}",
+                       f"(KPM count estimate {cnt:.1f}, 2048 moments), n_s={n_s}, n_b={n_b}, n_p={n_p}",
            "interval": [-delta, delta], "count_est_kpm": cnt}
     runs = {}
     for name, prec in (("fp64", 0), ("mixed", 1)):
-        M = M64 if prec == 0 else P.chebfd_matrix_build(*H, prec=1)
+        M = M64 if prec == 0 else P.chebfd_matrix_build(*H, prec=1, order=order)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = P.chebfd_solve(M, M64, -delta, delta, n_s, n_p, n_b, seed=43, max_iter=12, want_vectors=False)
@@ -189,7 +193,9 @@ def main():
     t0 = time.perf_counter()
     H = topi_csr(Nx, Ny, Nz, m=1.0, W=args.W, t=1.0, seed=1002)
     n, nnz = len(H[0]) - 1, len(H[1])
-    M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=prec)
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    order = lattice_row_order(Nx, Ny, Nz) if args.order == "lattice" else None
+    M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=prec, order=order)
     lo, hi = P.chebfd_bounds(M)
     lam = 0.1  # search interval [-0.1, 0.1] in H's units (the filter's cost does not depend on it)
     al, be, gam = P.chebfd_coefficients(lo, hi, -lam, lam, n_p)
@@ -229,8 +235,8 @@ def main():
     fbytes = traffic.filter_bytes(n, nnz, n_s, n_b, n_p, prec)
     gbs = fbytes / (filt_ms * 1e-3) / 1e9
     gflops = traffic.filter_flops(n, n_s, n_p, nnz / n) / (filt_ms * 1e-3) / 1e9
-    # dominant kernel: the fused step (n_p - 2 of every n_p launches of a block), timed
-    # alone: op_launches launches on three blocks of the start block, events on the stream
+    # the fused step also timed alone: op_launches back-to-back launches on three blocks
+    # of the start block (no partials of a previous launch to reduce), events on the stream
     xv = xy.view(n_s // n_b, n, n_b)
     opw = P.device_buffer(P.chebfd_filter_query(M, n_b))
     opb = opw.numel()
@@ -242,10 +248,13 @@ def main():
         P.chebfd_op(M, al, be, gam[3], n_b, xv[0], xv[1], xv[2], opw, opb)
     e1.record(stream)
     torch.cuda.synchronize()
-    avg_launch_s = e0.elapsed_time(e1) * 1e-3 / args.op_launches
+    op_alone_s = e0.elapsed_time(e1) * 1e-3 / args.op_launches
+    # the kernel's average launch over the timed region: every launch of a filter is
+    # this kernel (n_p - 2 fused steps and the two start launches of each block)
+    avg_launch_s = filt_ms * 1e-3 / ((n_s // n_b) * n_p)
     r, w = traffic.step_bytes(n, nnz, n_b, prec)
     achieved = (r + w) / avg_launch_s / 1e9
-    hbm = counter_traffic(prec, n_b, args.lattice)
+    hbm = counter_traffic(prec, n_b, args.lattice, args.order)
     del opw
 
     # attainable HBM bandwidth: copy probe over 2 x 2 GiB (the STREAM analogue of Table 2)
@@ -266,7 +275,7 @@ def main():
     if not args.no_solve:
         del xy, xb0, work
         torch.cuda.empty_cache()
-        solve = time_to_converged(P, H, Nx, Ny, Nz, args.W, n_s, n_b, n_p, args.solve_count)
+        solve = time_to_converged(P, H, Nx, Ny, Nz, args.W, n_s, n_b, n_p, args.solve_count, order)
 
     cpu = None
     if args.cpu_baseline_seconds > 0:
@@ -291,8 +300,9 @@ def main():
         "config": {
             "workload": f"Topi-{Nx}-{Ny}-{Nz} (n={n}, nnz={nnz}, W={args.W}), "
                         f"{'FP64' if prec == 0 else 'mixed c64'} full filter, n_s={n_s}, n_b={n_b}, "
-                        f"n_p={n_p}, SELL-32-256",
+                        f"n_p={n_p}, SELL-32-256, {args.order} row order",
             "n": n, "n_s": n_s, "n_b": n_b, "n_p": n_p, "prec": "fp64" if prec == 0 else "mixed",
+            "row_order": args.order,
         },
         "pct_of_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
         "gflops": round(gflops, 1),
@@ -303,6 +313,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": hbm,
             "kernel": f"cheb_lds_kernel<{'double' if prec == 0 else 'float'},{n_b},kModeStep>",
             "bytes_per_launch": r + w, "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "fused_step_alone_us": round(op_alone_s * 1e6, 3),
             "kernel_source_sha256_16": kernel_source_hash(),
         },
         "time_to_converged": solve,

@@ -218,16 +218,17 @@ def calibrate_kappa(inst: Instance, n_s: int, factors=(0.5, 0.75, 1.0, 1.5, 2.0,
     H, M = build(inst)
     lo, hi = P.chebfd_bounds(M)
     delta = inst.half_width * 2.0 / (hi - lo)
-    best = None
+    runs = []
     for kf in factors:
         n_p = int(round(kf / delta))
         r, dt = run(M, inst, n_p, n_s, max_iter=20)
         w = work_units(M.n, len(H[1]), n_p, n_s, r.stats.iterations)
         log(f"# kappa {kf}: n_p {n_p} status {r.status} iters {r.stats.iterations} found {r.n_found} "
             f"{dt:.2f}s work {w:.3e}")
-        if r.status == 0 and (best is None or w < best[1]):
-            best = (kf, w)
-    return best[0] if best else 1.0
+        runs.append((kf, w, r.status, r.n_found))
+    full = max(x[3] for x in runs)
+    ok = [x for x in runs if x[2] == 0 and x[3] == full]
+    return min(ok, key=lambda x: x[1])[0] if ok else 1.0
 
 
 def main(argv=None):
