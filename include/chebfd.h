@@ -246,8 +246,9 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
  * residual ||H z - theta z|| (||z|| = 1) is <= tol and spurious if its residual
  * exceeds (lam_R - lam_L) / 2; the iteration stops when the number of converged
  * pairs repeats and every pair in the interval is converged or spurious
- * (status CHEBFD_OK), after max_iter iterations (CHEBFD_NOT_CONVERGED), or when
- * more than 3/4 n_s Ritz values fall in the interval (CHEBFD_SUBSPACE_SMALL).
+ * (status CHEBFD_OK), after max_iter iterations (CHEBFD_NOT_CONVERGED), or when,
+ * from the second iteration on, more than 3/4 n_s non-spurious Ritz pairs fall in
+ * the interval (CHEBFD_SUBSPACE_SMALL).
  *
  * Mixed precision (p->prec MIXED): the c64 basis bounds the residuals below by
  * about 2^-24 |lambda - theta|.  The iteration therefore runs in two stages:

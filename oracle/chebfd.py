@@ -311,8 +311,9 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
     which symmetric filters on +-symmetric spectra keep producing).  The solve
     stops (status 0) when the number of converged pairs repeats the previous
     iteration's and every in-interval pair is converged or spurious; else after
-    max_iter iterations (status 1).  If the number of Ritz values inside the
-    interval exceeds 3/4 n_s the subspace is too small (status 2).  The paper
+    max_iter iterations (status 1).  If, from the second iteration on, the
+    number of non-spurious Ritz pairs inside the interval exceeds 3/4 n_s the
+    subspace is too small (status 2).  The paper
     gives none of these rules; they are the readings adopted here.  Refill
     vectors of iteration k are random_phase_block(n, d, refill_seed, col0=k n_s).
     Returns the converged pairs first (ascending), then the rest (ascending).
@@ -344,7 +345,9 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
         conv = inwin & (res <= tol)
         spurious = inwin & (res > 0.5 * (lam_R - lam_L))
         cnt = int(np.count_nonzero(conv))
-        if np.count_nonzero(inwin) > 0.75 * n_s:
+        # too many eigenvalues for the subspace: from the second iteration on, counted on
+        # the non-spurious pairs in the interval (a weak first filter scatters Ritz values)
+        if it >= 2 and np.count_nonzero(inwin & ~spurious) > 0.75 * n_s:
             status = 2
             break
         if cnt == prev and np.all(conv | spurious | ~inwin):

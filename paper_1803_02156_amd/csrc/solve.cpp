@@ -402,7 +402,7 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
             }
 
             // --- convergence test ---
-            int inwin = 0, conv = 0;
+            int inwin = 0, conv = 0, settled = 0;
             bool all_ok = true;
             double worst = 0.0;
             for (int c = 0; c < k2; ++c) {
@@ -411,10 +411,13 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
                 const bool cv = hres[c] <= g.tol;
                 const bool spur = hres[c] > 0.5 * (p->lam_R - p->lam_L);
                 conv += cv ? 1 : 0;
+                settled += spur ? 0 : 1;
                 all_ok = all_ok && (cv || spur);
                 if (!spur) worst = std::max(worst, hres[c]);
             }
-            if (stage1 && inwin > 0.75 * g.ns) return CHEBFD_SUBSPACE_SMALL;
+            // too many eigenvalues for the subspace: judged from the second iteration on, on
+            // the in-interval pairs whose residual already places them in the interval
+            if (stage1 && it >= 2 && settled > 0.75 * g.ns) return CHEBFD_SUBSPACE_SMALL;
             if (conv == prev && all_ok) return CHEBFD_OK;
             // stage 1 of a mixed run also ends when the residuals stop falling (storage floor)
             if (stage1 && g.prec != CHEBFD_PREC_FP64 && inwin > 0 && inwin == prev_inwin && conv == prev &&

@@ -49,14 +49,39 @@ class Instance:
     W: float
     half_width: float      # search interval [-hw, hw] in H's units
     seed: int
+    target: float = 0.0    # eigenvalue count the interval was sized for (0: half_width drawn directly)
 
 
-def sample_instance(rng: np.random.Generator, ext_lo: int, ext_hi: int, seed: int) -> Instance:
+def sample_instance(rng: np.random.Generator, ext_lo: int, ext_hi: int, seed: int,
+                    count_range=None) -> Instance:
     """A Topi instance: extents in [ext_lo, ext_hi] with a random aspect ratio,
-    m ~ U[0.5, 2.5], W ~ U[0, 3], interval half width ~ U[0.01, 0.1]."""
+    m ~ U[0.5, 2.5], W ~ U[0, 3].  The interval half width is ~ U[0.01, 0.1], or,
+    with count_range, sized later (``size_interval``) for a count ~ U[count_range]:
+    on small lattices most fixed-width windows near 0 hold no eigenvalue at all."""
     dims = tuple(int(v) for v in rng.integers(ext_lo, ext_hi + 1, 3))
-    return Instance(dims=dims, m=float(rng.uniform(0.5, 2.5)), W=float(rng.uniform(0.0, 3.0)),
-                    half_width=float(rng.uniform(0.01, 0.1)), seed=int(seed))
+    m, W = float(rng.uniform(0.5, 2.5)), float(rng.uniform(0.0, 3.0))
+    if count_range is None:
+        return Instance(dims=dims, m=m, W=W, half_width=float(rng.uniform(0.01, 0.1)), seed=int(seed))
+    return Instance(dims=dims, m=m, W=W, half_width=0.0, seed=int(seed),
+                    target=float(rng.uniform(*count_range)))
+
+
+def size_interval(M, target: float, seed: int, n_steps: int = 256, R: int = 16) -> float:
+    """Half width of the symmetric interval whose KPM count estimate (2 n_steps
+    moments, Jackson-damped window) is `target` (bisection on the host)."""
+    lo, hi = P.chebfd_bounds(M)
+    al, be, _ = P.chebfd_coefficients(lo, hi, -1e-3, 1e-3, 1)
+    mu = P.chebfd_kpm_moments(M, al, be, n_steps, R, seed)
+    half = max(abs(lo), abs(hi))
+    a, b = 1e-4 * half, 0.9 * half
+    for _ in range(50):
+        mid = 0.5 * (a + b)
+        _, _, gc = P.chebfd_coefficients(lo, hi, -mid, mid, 2 * n_steps - 1)
+        if M.n * float(np.dot(gc, mu)) < target:
+            a = mid
+        else:
+            b = mid
+    return 0.5 * (a + b)
 
 
 def build(inst: Instance, prec: int = _abi.PREC_FP64):
@@ -84,13 +109,15 @@ def grid(heur_np: int, heur_ns: int):
     return [(a, b) for a in nps for b in nss]
 
 
-def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, log=print):
+def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, count_range=None, log=print):
     """Features, heuristic choice, grid runs and labels of `count` instances."""
     rng = np.random.default_rng(seed)
     rows = []
     for k in range(count):
-        inst = sample_instance(rng, ext_lo, ext_hi, seed * 100000 + k)
+        inst = sample_instance(rng, ext_lo, ext_hi, seed * 100000 + k, count_range)
         H, M = build(inst)
+        if inst.target > 0:
+            inst.half_width = size_interval(M, inst.target, seed=1000 + k)
         n, nnz = M.n, len(H[1])
         f, cnt, al, be = P.chebfd_features(M, -inst.half_width, inst.half_width, seed=7 + k)
         a, b = f[256], f[257]
@@ -240,6 +267,8 @@ def main(argv=None):
     c.add_argument("--seed", type=int, required=True)
     c.add_argument("--ext", type=int, nargs=2, default=(12, 24))
     c.add_argument("--kappa", type=float, required=True)
+    c.add_argument("--counts", type=float, nargs=2, default=None,
+                   help="size each interval for an eigenvalue count drawn from this range")
     c.add_argument("--out", required=True)
     k = sub.add_parser("kappa")
     k.add_argument("--dims", type=int, nargs=3, default=(16, 16, 8))
@@ -260,7 +289,8 @@ def main(argv=None):
         inst = Instance(dims=tuple(a.dims), m=1.0, W=1.0, half_width=0.05, seed=1001)
         log(json.dumps({"kappa": calibrate_kappa(inst, 32, log=log)}))
     elif a.cmd == "corpus":
-        rows = make_corpus(a.count, a.seed, a.ext[0], a.ext[1], a.kappa, log=log)
+        rows = make_corpus(a.count, a.seed, a.ext[0], a.ext[1], a.kappa,
+                           count_range=None if a.counts is None else tuple(a.counts), log=log)
         with open(a.out, "w") as f:
             json.dump(rows, f)
     elif a.cmd == "train":
