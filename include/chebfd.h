@@ -245,7 +245,8 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
  * A Ritz pair inside the closed interval [lam_L, lam_R] is converged if its
  * residual ||H z - theta z|| (||z|| = 1) is <= tol and spurious if its residual
  * exceeds (lam_R - lam_L) / 2; the iteration stops when the number of converged
- * pairs repeats and every pair in the interval is converged or spurious
+ * pairs repeats, every pair in the interval is converged or spurious and the
+ * smallest spurious residual did not halve since the previous iteration
  * (status CHEBFD_OK), after max_iter iterations (CHEBFD_NOT_CONVERGED), or when,
  * from the second iteration on, more than 3/4 n_s non-spurious Ritz pairs fall in
  * the interval (CHEBFD_SUBSPACE_SMALL).

@@ -310,7 +310,8 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
     indicates no eigenvalue in it: a mixture of eigenvectors from both sides,
     which symmetric filters on +-symmetric spectra keep producing).  The solve
     stops (status 0) when the number of converged pairs repeats the previous
-    iteration's and every in-interval pair is converged or spurious; else after
+    iteration's, every in-interval pair is converged or spurious, and the
+    smallest spurious residual did not halve since the previous iteration; else after
     max_iter iterations (status 1).  If, from the second iteration on, the
     number of non-spurious Ritz pairs inside the interval exceeds 3/4 n_s the
     subspace is too small (status 2).  The paper
@@ -331,6 +332,7 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
     status = 1
     it = 0
     dropped = 0
+    prev_spur = np.inf
     for it in range(1, max_iter + 1):
         Y, eta, nu = chebyshev_filter(H, alpha, beta, gamma, X, n_b)
         if it == 1:
@@ -350,10 +352,16 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
         if it >= 2 and np.count_nonzero(inwin & ~spurious) > 0.75 * n_s:
             status = 2
             break
-        if cnt == prev and np.all(conv | spurious | ~inwin):
+        # spurious pairs count as settled only once their residuals stop falling: a filter
+        # that has not yet resolved the interval leaves every pair there with a large but
+        # shrinking residual
+        spur_min = float(np.min(res[spurious])) if np.any(spurious) else np.inf
+        spur_settled = not np.any(spurious) or spur_min > 0.5 * prev_spur
+        if cnt == prev and np.all(conv | spurious | ~inwin) and spur_settled:
             status = 0
             break
         prev = cnt
+        prev_spur = spur_min
         X = Z
         if dropped:
             X = np.concatenate([Z, random_phase_block(n, dropped, refill_seed, col0=it * n_s)], axis=1)

@@ -344,8 +344,10 @@ __global__ __launch_bounds__(kJT) void jacobi_kernel(int m, double *A, int lda, 
             }
             __syncthreads();
             // rows: A(p,:) <- c A(p,:) - s e^{i phi} A(q,:); A(q,:) <- s A(p,:) + c e^{i phi} A(q,:)
+            // consecutive threads take consecutive pairs of one column: their reads and
+            // writes stay inside that column (contiguous in memory)
             for (int t = tid; t < half * m; t += kJT) {
-                const int k = t / m, cl = t % m;
+                const int k = t % half, cl = t / half;
                 const int p = s_p[k], q = s_q[k];
                 if (q >= m) continue;
                 const double c = s_c[k], sr = s_sr[k], si = -s_si[k];  // s e^{+i phi}
