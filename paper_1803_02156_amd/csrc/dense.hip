@@ -15,6 +15,7 @@
 // D[l / 16 + 4 r][l % 16] in its r-th accumulator (r = 0..3; measured on gfx950).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "common.h"
@@ -235,19 +236,24 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int prec_a, i
 }
 
 // ---------------------------------------------------------------------------
-// Cyclic Jacobi eigensolver for a Hermitian m x m FP64 complex matrix (one
-// workgroup).  Rounds of the round-robin ordering rotate m/2 disjoint (p, q)
-// pairs: all rotation parameters of a round are formed first, then the column
-// rotations A <- A J and V <- V J, then the row rotations A <- J^H A.
-// For the pair block [[a, b], [conj(b), d]], b = |b| e^{i phi}, the rotation is
+// Cyclic Jacobi eigensolver for a Hermitian m x m FP64 complex matrix.
+// A sweep is me - 1 rounds (me = m rounded up to even) of the round-robin
+// ordering; a round rotates me/2 disjoint (p, q) pairs.  For the pair block
+// [[a, b], [conj(b), d]], b = |b| e^{i phi}, the rotation is
 // J = diag(1, e^{-i phi}) [[c, s], [-s, c]] with t = s / c the smaller root of
-// t^2 + 2 zeta t - 1 = 0, zeta = (d - a) / (2 |b|).
-// A is overwritten; w receives the eigenvalues ascending, V (ld) the
-// eigenvectors in the same order.  info[0] = sweeps used, info[1] = 1 if the
-// off-diagonal norm did not reach the tolerance.
+// t^2 + 2 zeta t - 1 = 0, zeta = (d - a) / (2 |b|); A <- J^H A J, V <- V J.
+//
+// One launch per round, one workgroup per pair: the workgroup first applies the
+// previous round's row rotations (A <- J^H A, every pair) to its own two
+// columns -- each column belongs to exactly one pair of every round, so every
+// column receives them -- then forms its rotation from the updated columns and
+// applies the column rotation to A and V.  The last round of a sweep is closed
+// by a launch that applies its row rotations to all columns.  The rotated pair's
+// off-diagonal entries are stored as exact zeros and its diagonal as real.
 // ---------------------------------------------------------------------------
-constexpr int kJT = 1024;
 constexpr int kMaxM = 512;
+constexpr int kJW = 256;       // threads per Jacobi workgroup
+constexpr int kJNormG = 64;    // workgroups of the norm reduction
 
 __device__ inline int rr_player(int m, int r, int k) {
     // round r, seat k of the circle method over players 0..m-1 (m even):
@@ -255,147 +261,149 @@ __device__ inline int rr_player(int m, int r, int k) {
     return k == 0 ? 0 : ((k - 1 + r) % (m - 1)) + 1;
 }
 
-__global__ __launch_bounds__(kJT) void jacobi_kernel(int m, double *A, int lda, double *V, int ldv,
-                                                     double *w, int max_sweeps, double tol,
-                                                     int *info, double *scratch) {
-    __shared__ double s_c[kMaxM / 2], s_sr[kMaxM / 2], s_si[kMaxM / 2];
-    __shared__ int s_p[kMaxM / 2], s_q[kMaxM / 2];
-    __shared__ double s_red[kJT];
-    __shared__ int s_done;
+struct JacobiRound {
+    int *p, *q;           // [2][kMaxM / 2] pair indices (p < q; q >= m: no rotation)
+    double *c, *sr, *si;  // [2][kMaxM / 2] c and s e^{-i phi}
+};
+
+// rows p, q of column `col` <- J^H (rows p, q) for the rotation in slot `slot`, pair kk
+__device__ inline void jacobi_row_rotate(double2 *Ac, int lda, const JacobiRound &jr, int slot, int kk, int col,
+                                         int m) {
+    const int h = slot * (kMaxM / 2) + kk;
+    const int p = jr.p[h], q = jr.q[h];
+    if (q >= m) return;
+    const double c = jr.c[h], sr = jr.sr[h], si = -jr.si[h];  // s e^{+i phi}
+    const double s = sqrt(sr * sr + si * si);
+    const double er = s > 0.0 ? sr / s : 1.0, ei = s > 0.0 ? si / s : 0.0;
+    const double2 x = Ac[(int64_t)col * lda + p], y = Ac[(int64_t)col * lda + q];
+    double2 np, nq;
+    np.x = c * x.x - (sr * y.x - si * y.y);
+    np.y = c * x.y - (sr * y.y + si * y.x);
+    nq.x = s * x.x + c * (er * y.x - ei * y.y);
+    nq.y = s * x.y + c * (er * y.y + ei * y.x);
+    if (col == q) np = double2{0.0, 0.0};
+    if (col == p) {
+        nq = double2{0.0, 0.0};
+        np.y = 0.0;
+    }
+    if (col == q) nq.y = 0.0;
+    Ac[(int64_t)col * lda + p] = np;
+    Ac[(int64_t)col * lda + q] = nq;
+}
+
+__global__ __launch_bounds__(kJW) void jacobi_round_kernel(int m, int me, int r, int has_prev, double *A, int lda,
+                                                           double *V, int ldv, JacobiRound jr) {
+    __shared__ double s_par[3];
     double2 *Ac = reinterpret_cast<double2 *>(A);
     double2 *Vc = reinterpret_cast<double2 *>(V);
-    const int tid = threadIdx.x;
-    const int me = m + (m & 1);  // players (a dummy player m when m is odd)
-    const int half = me / 2;
+    const int half = me / 2, k = blockIdx.x, tid = threadIdx.x;
+    int p = rr_player(me, r, k), q = rr_player(me, r, me - 1 - k);
+    if (p > q) { const int tmp = p; p = q; q = tmp; }
+    const int cur = r & 1, prv = cur ^ 1;
+    // (a) the previous round's row rotations on columns p and q
+    if (has_prev) {
+        for (int t = tid; t < 2 * half; t += kJW) {
+            const int col = t < half ? p : q;
+            if (col < m) jacobi_row_rotate(Ac, lda, jr, prv, t % half, col, m);
+        }
+    }
+    __syncthreads();
+    // (b) this round's rotation from the updated columns
+    if (tid == 0) {
+        double c = 1.0, sr = 0.0, si = 0.0;
+        if (q < m) {
+            const double a = Ac[(int64_t)p * lda + p].x;
+            const double d = Ac[(int64_t)q * lda + q].x;
+            const double2 b = Ac[(int64_t)q * lda + p];  // A[p][q]
+            const double ab = sqrt(b.x * b.x + b.y * b.y);
+            if (ab > 0.0) {
+                const double zeta = (d - a) / (2.0 * ab);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                c = 1.0 / sqrt(1.0 + t * t);
+                const double sn = t * c;
+                sr = sn * b.x / ab;   // s e^{-i phi} = s conj(b) / |b|
+                si = -sn * b.y / ab;
+            }
+        }
+        const int h = cur * (kMaxM / 2) + k;
+        jr.p[h] = p;
+        jr.q[h] = q;
+        jr.c[h] = c;
+        jr.sr[h] = sr;
+        jr.si[h] = si;
+        s_par[0] = c;
+        s_par[1] = sr;
+        s_par[2] = si;
+    }
+    __syncthreads();
+    if (q >= m) return;
+    // (c) columns: A(:,p) <- c A(:,p) - s e^{-i phi} A(:,q); A(:,q) <- s A(:,p) + c e^{-i phi} A(:,q); same for V
+    const double c = s_par[0], sr = s_par[1], si = s_par[2];
+    const double s = sqrt(sr * sr + si * si);
+    const double er = s > 0.0 ? sr / s : 1.0, ei = s > 0.0 ? si / s : 0.0;
+    for (int t = tid; t < 2 * m; t += kJW) {
+        const int which = t / m, row = t % m;
+        double2 *M = which ? Vc : Ac;
+        const int ld = which ? ldv : lda;
+        const double2 x = M[(int64_t)p * ld + row], y = M[(int64_t)q * ld + row];
+        double2 np, nq;
+        np.x = c * x.x - (sr * y.x - si * y.y);
+        np.y = c * x.y - (sr * y.y + si * y.x);
+        nq.x = s * x.x + c * (er * y.x - ei * y.y);
+        nq.y = s * x.y + c * (er * y.y + ei * y.x);
+        M[(int64_t)p * ld + row] = np;
+        M[(int64_t)q * ld + row] = nq;
+    }
+}
 
-    for (int t = tid; t < m * m; t += kJT) {
+// the row rotations of round slot `slot` on every column (closes a sweep)
+__global__ __launch_bounds__(kJW) void jacobi_rows_kernel(int m, int me, int slot, double *A, int lda,
+                                                          JacobiRound jr) {
+    double2 *Ac = reinterpret_cast<double2 *>(A);
+    const int half = me / 2;
+    for (int col = blockIdx.x; col < m; col += gridDim.x)
+        for (int t = threadIdx.x; t < half; t += kJW) jacobi_row_rotate(Ac, lda, jr, slot, t, col, m);
+}
+
+// partial sums of |A_ij|^2 (off-diagonal only if `off`), one per workgroup, fixed order
+__global__ __launch_bounds__(kJW) void jacobi_norm_kernel(int m, const double *A, int lda, int off,
+                                                          double *part) {
+    __shared__ double sred[kJW];
+    const double2 *Ac = reinterpret_cast<const double2 *>(A);
+    double acc = 0.0;
+    for (int t = blockIdx.x * kJW + threadIdx.x; t < m * m; t += gridDim.x * kJW) {
+        const int r = t % m, c = t / m;
+        if (off && r == c) continue;
+        const double2 v = Ac[(int64_t)c * lda + r];
+        acc += v.x * v.x + v.y * v.y;
+    }
+    sred[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kJW / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sred[threadIdx.x] += sred[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sred[0];
+}
+
+__global__ __launch_bounds__(kJW) void jacobi_init_kernel(int m, double *V, int ldv) {
+    double2 *Vc = reinterpret_cast<double2 *>(V);
+    for (int t = blockIdx.x * kJW + threadIdx.x; t < m * m; t += gridDim.x * kJW) {
         const int r = t % m, c = t / m;
         Vc[(int64_t)c * ldv + r] = double2{r == c ? 1.0 : 0.0, 0.0};
     }
-    // Frobenius norm for the stopping test
-    double fr = 0.0;
-    for (int t = tid; t < m * m; t += kJT) {
-        const double2 v = Ac[(int64_t)(t / m) * lda + t % m];
-        fr += v.x * v.x + v.y * v.y;
-    }
-    s_red[tid] = fr;
-    __syncthreads();
-    for (int h = kJT / 2; h > 0; h >>= 1) {
-        if (tid < h) s_red[tid] += s_red[tid + h];
-        __syncthreads();
-    }
-    const double fro2 = s_red[0];
-    __syncthreads();
+}
 
-    int sweep = 0;
-    bool converged = m <= 1;
-    for (sweep = 0; sweep < max_sweeps && !converged && m > 1; ++sweep) {
-        for (int r = 0; r < me - 1; ++r) {
-            // rotation parameters of this round
-            for (int k = tid; k < half; k += kJT) {
-                int p = rr_player(me, r, k), q = rr_player(me, r, me - 1 - k);
-                if (p > q) { const int tmp = p; p = q; q = tmp; }
-                double c = 1.0, sr = 0.0, si = 0.0;
-                if (q < m) {
-                    const double a = Ac[(int64_t)p * lda + p].x;
-                    const double d = Ac[(int64_t)q * lda + q].x;
-                    const double2 b = Ac[(int64_t)q * lda + p];  // A[p][q]
-                    const double ab = sqrt(b.x * b.x + b.y * b.y);
-                    if (ab > 0.0) {
-                        const double zeta = (d - a) / (2.0 * ab);
-                        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        const double s = t * c;
-                        // e^{-i phi} = conj(b) / |b|
-                        sr = s * b.x / ab;
-                        si = -s * b.y / ab;
-                    }
-                }
-                s_p[k] = p;
-                s_q[k] = q;
-                s_c[k] = c;
-                s_sr[k] = sr;  // s e^{-i phi}
-                s_si[k] = si;
-            }
-            __syncthreads();
-            // columns: A(:,p) <- c A(:,p) - s e^{-i phi} A(:,q); A(:,q) <- s A(:,p) + c e^{-i phi} A(:,q)
-            // (same for V), with s e^{-i phi} = (sr, si) and e^{-i phi} = (sr, si) / s
-            for (int t = tid; t < half * m; t += kJT) {
-                const int k = t / m, row = t % m;
-                const int p = s_p[k], q = s_q[k];
-                if (q >= m) continue;
-                const double c = s_c[k], sr = s_sr[k], si = s_si[k];
-                const double s = sqrt(sr * sr + si * si);
-                const double er = s > 0.0 ? sr / s : 1.0, ei = s > 0.0 ? si / s : 0.0;
-                for (int which = 0; which < 2; ++which) {
-                    double2 *M = which ? Vc : Ac;
-                    const int ld = which ? ldv : lda;
-                    const double2 x = M[(int64_t)p * ld + row], y = M[(int64_t)q * ld + row];
-                    double2 np, nq;
-                    // np = c x - (sr + i si) y
-                    np.x = c * x.x - (sr * y.x - si * y.y);
-                    np.y = c * x.y - (sr * y.y + si * y.x);
-                    // nq = s x + c (er + i ei) y
-                    nq.x = s * x.x + c * (er * y.x - ei * y.y);
-                    nq.y = s * x.y + c * (er * y.y + ei * y.x);
-                    M[(int64_t)p * ld + row] = np;
-                    M[(int64_t)q * ld + row] = nq;
-                }
-            }
-            __syncthreads();
-            // rows: A(p,:) <- c A(p,:) - s e^{i phi} A(q,:); A(q,:) <- s A(p,:) + c e^{i phi} A(q,:)
-            // consecutive threads take consecutive pairs of one column: their reads and
-            // writes stay inside that column (contiguous in memory)
-            for (int t = tid; t < half * m; t += kJT) {
-                const int k = t % half, cl = t / half;
-                const int p = s_p[k], q = s_q[k];
-                if (q >= m) continue;
-                const double c = s_c[k], sr = s_sr[k], si = -s_si[k];  // s e^{+i phi}
-                const double s = sqrt(sr * sr + si * si);
-                const double er = s > 0.0 ? sr / s : 1.0, ei = s > 0.0 ? si / s : 0.0;
-                const double2 x = Ac[(int64_t)cl * lda + p], y = Ac[(int64_t)cl * lda + q];
-                double2 np, nq;
-                np.x = c * x.x - (sr * y.x - si * y.y);
-                np.y = c * x.y - (sr * y.y + si * y.x);
-                nq.x = s * x.x + c * (er * y.x - ei * y.y);
-                nq.y = s * x.y + c * (er * y.y + ei * y.x);
-                // the pair's off-diagonal entries are annihilated by construction and
-                // its diagonal entries are real: store them exactly
-                if (cl == q) np = double2{0.0, 0.0};
-                if (cl == p) {
-                    nq = double2{0.0, 0.0};
-                    np.y = 0.0;
-                }
-                if (cl == q) nq.y = 0.0;
-                Ac[(int64_t)cl * lda + p] = np;
-                Ac[(int64_t)cl * lda + q] = nq;
-            }
-            __syncthreads();
-        }
-        // off-diagonal norm
-        double off = 0.0;
-        for (int t = tid; t < m * m; t += kJT) {
-            const int r = t % m, c = t / m;
-            if (r != c) {
-                const double2 v = Ac[(int64_t)c * lda + r];
-                off += v.x * v.x + v.y * v.y;
-            }
-        }
-        s_red[tid] = off;
-        __syncthreads();
-        for (int h = kJT / 2; h > 0; h >>= 1) {
-            if (tid < h) s_red[tid] += s_red[tid + h];
-            __syncthreads();
-        }
-        if (tid == 0) s_done = s_red[0] <= tol * tol * fro2 ? 1 : 0;
-        __syncthreads();
-        converged = s_done != 0;
-        __syncthreads();
-    }
-    // sort ascending (rank of each diagonal entry, ties by index), permute V
-    for (int t = tid; t < m; t += kJT) scratch[t] = Ac[(int64_t)t * lda + t].x;
+// eigenvalues ascending (ties by index) into w, eigenvectors permuted alike (one workgroup)
+__global__ __launch_bounds__(kJW) void jacobi_sort_kernel(int m, double *A, int lda, double *V, int ldv,
+                                                          double *w, double *scratch) {
+    double2 *Ac = reinterpret_cast<double2 *>(A);
+    double2 *Vc = reinterpret_cast<double2 *>(V);
+    int *rank_of = reinterpret_cast<int *>(scratch + m);
+    const int tid = threadIdx.x;
+    for (int t = tid; t < m; t += kJW) scratch[t] = Ac[(int64_t)t * lda + t].x;
     __syncthreads();
-    for (int t = tid; t < m; t += kJT) {
+    for (int t = tid; t < m; t += kJW) {
         const double d = scratch[t];
         int rank = 0;
         for (int u = 0; u < m; ++u) {
@@ -403,23 +411,18 @@ __global__ __launch_bounds__(kJT) void jacobi_kernel(int m, double *A, int lda, 
             rank += (e < d || (e == d && u < t)) ? 1 : 0;
         }
         w[rank] = d;
-        reinterpret_cast<int *>(scratch + m)[t] = rank;
+        rank_of[t] = rank;
     }
     __syncthreads();
     // permuted copy of V through A's storage (A is no longer needed)
-    for (int t = tid; t < m * m; t += kJT) {
+    for (int t = tid; t < m * m; t += kJW) {
         const int r = t % m, c = t / m;
-        const int rank = reinterpret_cast<const int *>(scratch + m)[c];
-        Ac[(int64_t)rank * lda + r] = Vc[(int64_t)c * ldv + r];
+        Ac[(int64_t)rank_of[c] * lda + r] = Vc[(int64_t)c * ldv + r];
     }
     __syncthreads();
-    for (int t = tid; t < m * m; t += kJT) {
+    for (int t = tid; t < m * m; t += kJW) {
         const int r = t % m, c = t / m;
         Vc[(int64_t)c * ldv + r] = Ac[(int64_t)c * lda + r];
-    }
-    if (tid == 0) {
-        info[0] = sweep;
-        info[1] = converged ? 0 : 1;
     }
 }
 
@@ -659,11 +662,62 @@ int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm,
     return CHEBFD_OK;
 }
 
-int launch_jacobi(int m, double *A, int lda, double *V, int ldv, double *w, int max_sweeps,
-                  double tol, int *info, double *scratch, hipStream_t s) {
-    if (m > kMaxM) CHEBFD_FAIL(CHEBFD_EINVAL, "eigensolver size %d > %d", m, kMaxM);
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJT), 0, s, m, A, lda, V, ldv, w, max_sweeps, tol,
-                       info, scratch);
+size_t jacobi_scratch_bytes(int m) {
+    (void)m;
+    // params [2][kMaxM/2] x (2 ints + 3 doubles), norm partials, sort scratch (2 kMaxM doubles)
+    return round_up(2 * (kMaxM / 2) * (2 * sizeof(int) + 3 * sizeof(double)), 256) +
+           round_up(kJNormG * sizeof(double), 256) + round_up(2 * kMaxM * sizeof(double), 256);
+}
+
+int launch_jacobi(int m, double *A, int lda, double *V, int ldv, double *w, int max_sweeps, double tol,
+                  void *scratch, int *sweeps, int *converged, hipStream_t s) {
+    if (m < 1 || m > kMaxM) CHEBFD_FAIL(CHEBFD_EINVAL, "eigensolver size %d not in [1, %d]", m, kMaxM);
+    char *base = static_cast<char *>(scratch);
+    const int H2 = 2 * (kMaxM / 2);
+    JacobiRound jr;
+    jr.p = reinterpret_cast<int *>(base);
+    jr.q = jr.p + H2;
+    jr.c = reinterpret_cast<double *>(base + round_up(2 * H2 * sizeof(int), 16));
+    jr.sr = jr.c + H2;
+    jr.si = jr.sr + H2;
+    double *part = reinterpret_cast<double *>(base + round_up(2 * (kMaxM / 2) * (2 * sizeof(int) + 3 * sizeof(double)), 256));
+    double *sortw = part + round_up(kJNormG * sizeof(double), 256) / sizeof(double);
+    const int me = m + (m & 1), half = me / 2;
+    const int G = std::min(kJNormG, std::max(1, (m * m + kJW - 1) / kJW));
+    double hp[kJNormG];
+    auto norm2 = [&](int off, double *out) -> int {
+        hipLaunchKernelGGL(jacobi_norm_kernel, dim3(G), dim3(kJW), 0, s, m, A, lda, off, part);
+        CHEBFD_HIP(hipGetLastError());
+        CHEBFD_HIP(hipMemcpyAsync(hp, part, sizeof(double) * G, hipMemcpyDeviceToHost, s));
+        CHEBFD_HIP(hipStreamSynchronize(s));
+        double acc = 0.0;
+        for (int g = 0; g < G; ++g) acc += hp[g];
+        *out = acc;
+        return CHEBFD_OK;
+    };
+    int rc;
+    hipLaunchKernelGGL(jacobi_init_kernel, dim3(std::min(1024, (m * m + kJW - 1) / kJW)), dim3(kJW), 0, s, m, V,
+                       ldv);
+    CHEBFD_HIP(hipGetLastError());
+    double fro2 = 0.0, off2 = 0.0;
+    if ((rc = norm2(0, &fro2))) return rc;
+    if ((rc = norm2(1, &off2))) return rc;
+    *converged = off2 <= tol * tol * fro2 ? 1 : 0;
+    int sweep = 0;
+    for (; sweep < max_sweeps && !*converged; ++sweep) {
+        for (int r = 0; r < me - 1; ++r) {
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3(half), dim3(kJW), 0, s, m, me, r, r > 0 ? 1 : 0, A, lda, V,
+                               ldv, jr);
+            CHEBFD_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(jacobi_rows_kernel, dim3(std::min(m, 256)), dim3(kJW), 0, s, m, me, (me - 2) & 1, A, lda,
+                           jr);
+        CHEBFD_HIP(hipGetLastError());
+        if ((rc = norm2(1, &off2))) return rc;
+        *converged = off2 <= tol * tol * fro2 ? 1 : 0;
+    }
+    *sweeps = sweep;
+    hipLaunchKernelGGL(jacobi_sort_kernel, dim3(1), dim3(kJW), 0, s, m, A, lda, V, ldv, w, sortw);
     CHEBFD_HIP(hipGetLastError());
     return CHEBFD_OK;
 }

@@ -72,8 +72,11 @@ int launch_gram(const void *A, int prec_a, int nb_a, const void *B, int prec_b, 
 size_t gram_part_bytes(int m1, int m2, int nsplit);
 int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm, void *Z, int prec_z,
                   int nb_z, int64_t n, int m1, int m2, hipStream_t s);
-int launch_jacobi(int m, double *A, int lda, double *V, int ldv, double *w, int max_sweeps,
-                  double tol, int *info, double *scratch, hipStream_t s);
+// Jacobi eigensolver (host-driven sweeps, one launch per round); synchronises `s`
+// once per sweep to read the off-diagonal norm
+size_t jacobi_scratch_bytes(int m);
+int launch_jacobi(int m, double *A, int lda, double *V, int ldv, double *w, int max_sweeps, double tol,
+                  void *scratch, int *sweeps, int *converged, hipStream_t s);
 
 int launch_svqb_scale(int m, double *S, int ld, double *d, hipStream_t s);
 int launch_svqb_transform(int m, int k, int first, const double *d, const double *V, int ldv,

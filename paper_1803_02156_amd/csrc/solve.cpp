@@ -169,7 +169,7 @@ int chebfd_update(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec_a
 int chebfd_heev_query(int32_t m, size_t *work_bytes) {
     clear_error();
     CHEBFD_REQUIRE(m >= 1 && m <= 512 && work_bytes, "eigensolver size %d not in [1, 512]", m);
-    *work_bytes = al(2 * (size_t)m * 8 + 64) + 256;
+    *work_bytes = al(jacobi_scratch_bytes(m));
     return CHEBFD_OK;
 }
 
@@ -181,15 +181,13 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
     if (rc) return rc;
     CHEBFD_REQUIRE(d_a && d_v && d_w && d_work && lda >= m && ldv >= m, "invalid eigensolver arguments");
     if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "eigensolver workspace %zu < %zu", work_bytes, need);
+    CHEBFD_REQUIRE(aligned(d_work, 256), "d_work must be 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int *info = static_cast<int *>(d_work);
-    double *scratch = reinterpret_cast<double *>(static_cast<char *>(d_work) + 256);
-    if ((rc = launch_jacobi(m, d_a, lda, d_v, ldv, d_w, 40, jacobi_tol(m), info, scratch, s))) return rc;
-    int h[2];
-    CHEBFD_HIP(hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, s));
-    CHEBFD_HIP(hipStreamSynchronize(s));
-    if (h_sweeps) *h_sweeps = h[0];
-    if (h[1]) CHEBFD_FAIL(CHEBFD_ENUMERIC, "Jacobi eigensolver did not converge in %d sweeps", h[0]);
+    int sweeps = 0, converged = 0;
+    if ((rc = launch_jacobi(m, d_a, lda, d_v, ldv, d_w, 40, jacobi_tol(m), d_work, &sweeps, &converged, s)))
+        return rc;
+    if (h_sweeps) *h_sweeps = sweeps;
+    if (!converged) CHEBFD_FAIL(CHEBFD_ENUMERIC, "Jacobi eigensolver did not converge in %d sweeps", sweeps);
     return CHEBFD_OK;
 }
 
