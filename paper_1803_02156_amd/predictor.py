@@ -104,7 +104,7 @@ def run(M, inst: Instance, n_p: int, n_s: int, max_iter: int = 12):
 
 
 def grid(heur_np: int, heur_ns: int):
-    nps = sorted({int(min(_abi.NP_MAX, max(_abi.NP_MIN, round(heur_np * f)))) for f in (0.5, 1.0, 2.0, 4.0)})
+    nps = sorted({int(min(_abi.NP_MAX, max(_abi.NP_MIN, round(heur_np * f)))) for f in (1.0, 2.0, 4.0, 8.0)})
     nss = sorted({heur_ns, min(512, heur_ns + N_B)})
     return [(a, b) for a in nps for b in nss]
 

@@ -1,0 +1,45 @@
+"""The trained parameter predictor against the plain heuristic on held-out instances:
+the network's (n_p, n_s) must find the interval's eigenpairs where the heuristic's
+choice fails, judged by the solver itself (status, pairs found, iterations)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1803_02156_amd", "data")
+
+
+@pytest.fixture(scope="module")
+def PR():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1803_02156_amd as P
+    P.load()
+    from paper_1803_02156_amd import predictor
+    return predictor
+
+
+def test_network_output_matches_oracle_forward(PR):
+    import oracle.mlp as OM
+    pred = PR.load(os.path.join(DATA, "predictor.npz"))
+    rows = json.load(open(os.path.join(DATA, "corpus_eval.json")))
+    X = np.array([r["features"] for r in rows], dtype=np.float32)
+    y = PR.predict(pred["params"], X)
+    ref, _ = OM.forward(pred["params"].astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(y - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_network_beats_heuristic_on_held_out_instances(PR):
+    pred = PR.load(os.path.join(DATA, "predictor.npz"))
+    rows = json.load(open(os.path.join(DATA, "corpus_eval.json")))[:10]
+    ev = PR.evaluate(pred, rows, pred["kappa"], log=lambda s: print(s, flush=True))
+    s = PR.summarise(ev)
+    print(s)
+    assert s["mlp"]["failures"] < s["heuristic"]["failures"]
+    # every instance the network solves has all of the interval's pairs, converged
+    for e in ev:
+        if not e["mlp"]["failed"]:
+            assert e["mlp"]["status"] == 0 and e["mlp"]["n_found"] >= e["full_count"]

@@ -18,9 +18,9 @@ def test_sampled_instances_cover_the_stated_ranges():
 
 def test_grid_is_clamped_and_contains_the_heuristic():
     g = PR.grid(400, 64)
-    assert (400, 64) in g and (200, 96) in g and (800, 64) in g and (1600, 96) in g and len(g) == 8
-    g = PR.grid(60, 512)
-    assert all(50 <= a <= 20000 and b <= 512 for a, b in g) and (50, 512) in g
+    assert (400, 64) in g and (800, 96) in g and (1600, 64) in g and (3200, 96) in g and len(g) == 8
+    g = PR.grid(30, 512)
+    assert all(50 <= a <= 20000 and b <= 512 for a, b in g) and (50, 512) in g and (240, 512) in g
 
 
 def test_standardise_round_trip():
