@@ -449,18 +449,22 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     Stage S2{H64, CHEBFD_PREC_FP64, 0, std::max(1, nb / 2), S1.Q, S1.X, D(L.b64), D(L.t64), p->tol};
     if (prec != CHEBFD_PREC_FP64 && status == CHEBFD_OK && it < p->max_iter) {
         // --- stage 2 (mixed precision): FP64 iteration on the Ritz vectors nearest the interval ---
-        std::vector<int> pick;
-        for (int c = 0; c < k2; ++c)
-            if (hth[c] >= p->lam_L && hth[c] <= p->lam_R) pick.push_back(c);
+        // the non-spurious pairs in the interval first, then the other Ritz vectors by
+        // distance of their values from the interval's centre
+        const double half_w = 0.5 * (p->lam_R - p->lam_L), mid = 0.5 * (p->lam_L + p->lam_R);
+        std::vector<int> pick, rest;
+        for (int c = 0; c < k2; ++c) {
+            if (hth[c] >= p->lam_L && hth[c] <= p->lam_R && hres[c] <= half_w)
+                pick.push_back(c);
+            else
+                rest.push_back(c);
+        }
         const int inwin = static_cast<int>(pick.size());
         const int ns2_max = ns / 2 / S2.nb * S2.nb;
         int ns2 = std::max(inwin + 2, (4 * inwin + 2) / 3 + 1);
         ns2 = std::min(ns2_max, (ns2 + S2.nb - 1) / S2.nb * S2.nb);
-        if (inwin > 0 && ns2 >= inwin && ns2 <= k2) {
-            const double mid = 0.5 * (p->lam_L + p->lam_R);
-            std::vector<int> rest;
-            for (int c = 0; c < k2; ++c)
-                if (!(hth[c] >= p->lam_L && hth[c] <= p->lam_R)) rest.push_back(c);
+        ns2 = std::min(ns2, k2 / S2.nb * S2.nb);
+        if (inwin > 0 && ns2 >= inwin) {
             std::stable_sort(rest.begin(), rest.end(),
                              [&](int a, int b) { return std::fabs(hth[a] - mid) < std::fabs(hth[b] - mid); });
             for (int c : rest)
