@@ -11,9 +11,11 @@ like the sigma sort of SELL-C-sigma itself):
 * the lattice is cut into ``parts`` boxes (one per L2 domain: the step kernel
   hands each of the eight XCDs of the device one contiguous eighth of the
   rows), and
-* inside a box, sites are taken in slabs of ``slab`` y-lines; a slab is swept
-  z-plane by z-plane, so a site's z-neighbours are one slab plane
-  (box_x * slab sites) away instead of a whole lattice plane.
+* inside a box, sites are taken in pencils of px x py sites swept along z, so a
+  site's z-neighbours are px py sites away instead of a whole lattice plane
+  (measured on the 128x128x64 lattice: HBM reads of a step 1.94 x the
+  algorithmic bytes in the natural order, 1.36 x with 8 x 4 pencils), or in
+  y-slabs swept z-plane by z-plane.
 
 Orbitals of a site stay consecutive (row = orbitals * site + orbital).
 """
@@ -36,12 +38,17 @@ def _split(dims, parts):
     return tuple(split)
 
 
-def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int = 8, slab: int = 8):
+def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int = 8, slab: int = 8,
+                      pencil=(8, 4)):
     """Row order (int32 permutation of 0..n-1, order[k] = original row placed k-th) for a
     lattice with site index x + Nx (y + Ny z) and row orbitals * site + orbital.
 
-    Falls back to fewer boxes when the extents do not split evenly, and to slabs of
-    the full box width in y when ``slab`` does not divide it."""
+    Inside a box, pencils of px x py sites (``pencil``, default 8 x 4) are swept
+    along z, so that z-neighbours are px py sites apart and x/y-neighbours are in
+    the same or an adjacent pencil; with ``pencil=None``, or when px, py do not
+    divide the box extents, y-slabs of ``slab`` lines are swept z-plane by z-plane
+    instead.  Falls back to fewer boxes when the extents do not split evenly, and
+    to slabs of the full box width when ``slab`` does not divide it."""
     dims = (int(Nx), int(Ny), int(Nz))
     split = None
     while parts >= 1 and split is None:
@@ -57,7 +64,13 @@ def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int =
     box = (x // bx) + px * ((y // by) + py * (z // bz))
     ly = y % by
     # lexsort: the last key is the primary one
-    key = np.lexsort((x % bx, ly, z % bz, ly // sy, box))
+    if pencil is not None and bx % pencil[0] == 0 and by % pencil[1] == 0:
+        # pencils of px x py sites swept along z: z-neighbours px py sites apart
+        px, py = pencil
+        lx = x % bx
+        key = np.lexsort((lx % px, ly % py, z % bz, lx // px, ly // py, box))
+    else:
+        key = np.lexsort((x % bx, ly, z % bz, ly // sy, box))
     sites = site[key]
     rows = (orbitals * sites[:, None] + np.arange(orbitals)[None, :]).ravel()
     return rows.astype(np.int32)

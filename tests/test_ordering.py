@@ -34,3 +34,17 @@ def test_neighbour_distances_shrink():
     for b in range(8):
         xs, ys, zs = sites_of[b] % Nx, (sites_of[b] // Nx) % Ny, sites_of[b] // (Nx * Ny)
         assert np.ptp(xs) < 64 and (np.ptp(xs) + 1) * (np.ptp(ys) + 1) * (np.ptp(zs) + 1) == box_rows // 4
+
+
+def test_pencil_order_keeps_z_neighbours_close():
+    Nx, Ny, Nz = 128, 128, 64
+    o = lattice_row_order(Nx, Ny, Nz)                      # 8 x 4 pencils
+    pos = np.empty(o.size, dtype=np.int64)
+    pos[o] = np.arange(o.size)
+    s = np.arange(Nx * Ny * Nz)
+    x, y, z = s % Nx, (s // Nx) % Ny, s // (Nx * Ny)
+    zn = x + Nx * (y + Ny * ((z + 1) % Nz))
+    d = np.abs(pos[4 * zn] - pos[4 * s])
+    assert np.median(d) == 4 * 8 * 4
+    o2 = lattice_row_order(6, 5, 4)                        # pencils do not divide: slabs
+    assert np.array_equal(np.sort(o2), np.arange(o2.size))
