@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables)")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-converged leg")
+    ap.add_argument("--solve-prec", choices=("both", "fp64", "mixed"), default="both",
+                    help="precisions of the time-to-converged leg")
     ap.add_argument("--solve-count", type=float, default=100.0,
                     help="eigenvalue count the symmetric search interval is sized for")
     ap.add_argument("--op-launches", type=int, default=200, help="launches of the fused step timed alone")
@@ -101,7 +103,7 @@ def interval_for_count(P, M, target, seed=7, n_steps=1024, R=16):
     return 0.5 * (a + b), count(0.5 * (a + b))
 
 
-def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target, order):
+def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target, order, which="both"):
     """Full ChebFD runs (filter, SVQB, Rayleigh-Ritz, residuals, restarts) in FP64 and
     mixed precision on the same matrix and interval; wall time from the first launch
     to the synchronised end, matrix build excluded."""
@@ -113,6 +115,8 @@ def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target, order):
            "interval": [-delta, delta], "count_est_kpm": cnt}
     runs = {}
     for name, prec in (("fp64", 0), ("mixed", 1)):
+        if which not in ("both", name):
+            continue
         M = M64 if prec == 0 else P.chebfd_matrix_build(*H, prec=1, order=order)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -133,11 +137,12 @@ def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target, order):
         print(f"# solve {name}: {dt:.2f} s, status {r.status}, {st.iterations} iterations, "
               f"{nf} pairs", file=sys.stderr, flush=True)
         del M
-    a, b = runs["fp64"], runs["mixed"]
-    if a.n_found == b.n_found and a.n_found > 0:
-        out["mixed"]["max_abs_dtheta_vs_fp64"] = float(np.max(np.abs(np.sort(a.theta[:a.n_found]) -
-                                                                      np.sort(b.theta[:b.n_found]))))
-    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    if len(runs) == 2:
+        a, b = runs["fp64"], runs["mixed"]
+        if a.n_found == b.n_found and a.n_found > 0:
+            out["mixed"]["max_abs_dtheta_vs_fp64"] = float(np.max(np.abs(np.sort(a.theta[:a.n_found]) -
+                                                                          np.sort(b.theta[:b.n_found]))))
+        out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
     return out
 
 
@@ -256,6 +261,16 @@ def main():
     achieved = (r + w) / avg_launch_s / 1e9
     hbm = counter_traffic(prec, n_b, args.lattice, args.order)
     del opw
+    # the orthogonalisation's Gram product Y^H Y over the whole search block (FP64 MFMA)
+    P.chebfd_gram(xy.view(n_s // n_b, n, n_b), xy.view(n_s // n_b, n, n_b))
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(5):
+        P.chebfd_gram(xy.view(n_s // n_b, n, n_b), xy.view(n_s // n_b, n, n_b))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gram_ms = e0.elapsed_time(e1) / 5
+    gram_tflops = 8.0 * n * n_s * n_s / (gram_ms * 1e-3) / 1e12
 
     # attainable HBM bandwidth: copy probe over 2 x 2 GiB (the STREAM analogue of Table 2)
     cnt = 1 << 28
@@ -275,7 +290,8 @@ def main():
     if not args.no_solve:
         del xy, xb0, work
         torch.cuda.empty_cache()
-        solve = time_to_converged(P, H, Nx, Ny, Nz, args.W, n_s, n_b, n_p, args.solve_count, order)
+        solve = time_to_converged(P, H, Nx, Ny, Nz, args.W, n_s, n_b, n_p, args.solve_count, order,
+                                  args.solve_prec)
 
     cpu = None
     if args.cpu_baseline_seconds > 0:
@@ -316,6 +332,9 @@ def main():
             "fused_step_alone_us": round(op_alone_s * 1e6, 3),
             "kernel_source_sha256_16": kernel_source_hash(),
         },
+        "gram": {"kernel": "gram_kernel (FP64 MFMA 16x16x4)", "shape": f"{n} x {n_s} x {n_s} complex",
+                 "ms": round(gram_ms, 3), "tflops": round(gram_tflops, 2),
+                 "frac_of_fp64_mfma_peak": round(gram_tflops / 78.6, 4)},
         "time_to_converged": solve,
         "cpu_baseline": cpu,
     }

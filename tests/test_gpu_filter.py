@@ -166,39 +166,49 @@ def test_filter_chebyshev_identity_large(P, prec):
         assert np.max(np.abs(nu[p] - ref)) <= n * 4 * _bound(p, 1, u, np.cos(0.2))
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_single_step_full_size_sampled_rows(P, prec):
-    # one chebfd_op step at the 64x64x32 configuration (n = 524288, n_b = 32,
-    # SELL-32-256) in the benchmark's launch geometry; sampled rows recomputed
-    # from the CRS arrays in FP64
-    H = topi_csr(64, 64, 32, m=1.0, W=1.0, seed=1002)
+@pytest.mark.parametrize("dims,W,order_kind,prec", [
+    ((64, 64, 32), 1.0, "lattice", 0),      # the benchmark's matrix, row order and launch geometry
+    ((64, 64, 32), 1.0, "lattice", 1),
+    ((64, 64, 32), 1.0, "natural", 0),
+    ((128, 128, 64), 1.5, "lattice", 1),    # the 128x128x64 mixed-precision configuration
+    ((128, 128, 64), 1.5, "lattice", 0),
+])
+def test_single_step_full_size_sampled_rows(P, dims, W, order_kind, prec):
+    # one chebfd_op step at full size (n_b = 32, SELL-32-256); sampled rows
+    # recomputed from the CRS arrays in FP64
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    H = topi_csr(*dims, m=1.0, W=W, seed=1002)
     n, n_b = len(H[0]) - 1, 32
-    M = P.chebfd_matrix_build(*H, prec=prec)
+    order = lattice_row_order(*dims) if order_kind == "lattice" else None
+    M = P.chebfd_matrix_build(*H, prec=prec, order=order)
     rng = np.random.default_rng(0)
-    dt = P.vec_dtype(prec)
-    U = (rng.standard_normal((n, n_b)) + 1j * rng.standard_normal((n, n_b))).astype(np.complex128)
-    W = (rng.standard_normal((n, n_b)) + 1j * rng.standard_normal((n, n_b))).astype(np.complex128)
-    Yh = (rng.standard_normal((n, n_b)) + 1j * rng.standard_normal((n, n_b))).astype(np.complex128)
+
+    def dev(A):   # original-order host block -> the kernel's permuted blocked layout
+        return P.chebfd_pack(M, _to_dev_colmajor(A), n_b, prec=prec)[0]
+
+    U = (rng.standard_normal((n, n_b)) + 1j * rng.standard_normal((n, n_b)))
+    W0 = (rng.standard_normal((n, n_b)) + 1j * rng.standard_normal((n, n_b)))
+    Yh = (rng.standard_normal((n, n_b)) + 1j * rng.standard_normal((n, n_b)))
     if prec == 1:   # the kernel sees the c64-rounded inputs
-        U, W, Yh = (a.astype(np.complex64).astype(np.complex128) for a in (U, W, Yh))
-    u = torch.from_numpy(U).to("cuda", dt)
-    w = torch.from_numpy(W).to("cuda", dt)
-    y = torch.from_numpy(Yh).to("cuda", dt)
+        U, W0, Yh = (a.astype(np.complex64).astype(np.complex128) for a in (U, W0, Yh))
+    u, w, y = dev(U), dev(W0), dev(Yh)
     nbytes = P.chebfd_filter_query(M, n_b)
     work = P.device_buffer(nbytes)
     al, be, g = 0.1333, 0.0, -0.37
     P.chebfd_op(M, al, be, g, n_b, u, w, y, work, nbytes)
-    Wg, Yg = w.cpu().numpy().astype(np.complex128), y.cpu().numpy().astype(np.complex128)
+    Wg = P.chebfd_unpack(M, w.reshape(1, n, n_b)).cpu().numpy()
+    Yg = P.chebfd_unpack(M, y.reshape(1, n, n_b)).cpu().numpy()
+    del u, w, y
     rows = np.concatenate([[0, 1, n - 1], rng.integers(0, n, 2000)])
     rowptr, col, val = H
     if prec == 1:
         val = val.astype(np.complex64).astype(np.complex128)
+    uu = EPS64 if prec == 0 else EPS32
     for i in rows:
         sl = slice(rowptr[i], rowptr[i + 1])
         hu = al * (val[sl] @ U[col[sl]]) + be * U[i]
-        wn = 2 * hu - W[i]
-        scale = np.sum(np.abs(val[sl])[:, None] * np.abs(U[col[sl]]), axis=0) * 2 * al + np.abs(W[i])
-        uu = EPS64 if prec == 0 else EPS32
+        wn = 2 * hu - W0[i]
+        scale = np.sum(np.abs(val[sl])[:, None] * np.abs(U[col[sl]]), axis=0) * 2 * al + np.abs(W0[i])
         assert np.all(np.abs(Wg[i] - wn) <= 20 * uu * (scale + 1e-300))
         assert np.all(np.abs(Yg[i] - (Yh[i] + g * wn)) <= 20 * uu * (np.abs(Yh[i]) + abs(g) * scale))
 
