@@ -59,10 +59,57 @@ __device__ inline void st_nt(float2 *p, float2 r) {
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;
 
-// Prefetch registers per thread: a tile holds max(32, 256 / NB) rows of at
-// most 16 slots (wider rows or chunks above 32 rows use the other kernels).
-constexpr int lds_prefetch_slots(int nb) {
-    return (((256 / nb) > 32 ? (256 / nb) : 32) * 16 + kThreads - 1) / kThreads;
+// Columns per lane: c64 blocks give each lane two adjacent columns (one
+// 16-byte access per row segment instead of two 8-byte ones: the gathers are
+// bound by the number of vector memory instructions as much as by bytes).
+template <typename T, int NB>
+constexpr int cols_per_lane() { return (sizeof(T) == 4 && NB >= 2) ? 2 : 1; }
+
+// CPL complex numbers of one lane: re[c], im[c] of columns jc + c
+template <typename T, int CPL> struct Pack {
+    T re[CPL], im[CPL];
+};
+
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int CPL, bool NT>
+__device__ inline Pack<T, CPL> load_pack(const T *p) {  // p: interleaved re, im of CPL columns
+    Pack<T, CPL> r;
+    if constexpr (CPL == 2) {
+        const fv4 v = NT ? __builtin_nontemporal_load(reinterpret_cast<const fv4 *>(p))
+                         : *reinterpret_cast<const fv4 *>(p);
+        r.re[0] = v.x;
+        r.im[0] = v.y;
+        r.re[1] = v.z;
+        r.im[1] = v.w;
+    } else {
+        using VT = typename V2<T>::type;
+        const VT v = NT ? ld_nt(reinterpret_cast<const VT *>(p)) : *reinterpret_cast<const VT *>(p);
+        r.re[0] = v.x;
+        r.im[0] = v.y;
+    }
+    return r;
+}
+
+template <typename T, int CPL>
+__device__ inline void store_pack_nt(T *p, const Pack<T, CPL> &r) {
+    if constexpr (CPL == 2) {
+        fv4 v;
+        v.x = r.re[0];
+        v.y = r.im[0];
+        v.z = r.re[1];
+        v.w = r.im[1];
+        __builtin_nontemporal_store(v, reinterpret_cast<fv4 *>(p));
+    } else {
+        using VT = typename V2<T>::type;
+        st_nt(reinterpret_cast<VT *>(p), VT{r.re[0], r.im[0]});
+    }
+}
+
+// Prefetch registers per thread: a tile holds max(32, rows per sub-pass) rows
+// of at most 16 slots (wider rows or chunks above 32 rows use the other kernels).
+constexpr int lds_prefetch_slots(int rows) {
+    return ((rows > 32 ? rows : 32) * 16 + kThreads - 1) / kThreads;
 }
 constexpr int kMaxTileWidth = 16;
 
@@ -98,14 +145,17 @@ template <typename T, int NB, int MODE, int MAXW>
 __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile_rows, int tile_slots,
                                                             int64_t ntiles) {
     using VT = typename V2<T>::type;
-    constexpr int ROWS = kThreads / NB;
-    constexpr int PF = lds_prefetch_slots(NB);
+    constexpr int CPL = cols_per_lane<T, NB>();
+    constexpr int LPR = NB / CPL;              // lanes per row
+    constexpr int ROWS = kThreads / LPR;       // rows per sub-pass
+    constexpr int PF = lds_prefetch_slots(ROWS);
+    using PK = Pack<T, CPL>;
     extern __shared__ __align__(16) unsigned char smem[];
     double *sred = reinterpret_cast<double *>(smem);
     // byte offsets of the two tile buffers inside smem (pointers are formed
     // from smem at each use so the compiler keeps them in the LDS address space)
     const int cpt = tile_rows >> a.log2C;
-    const int o_vals = static_cast<int>(sizeof(double)) * 3 * kThreads;
+    const int o_vals = static_cast<int>(sizeof(double)) * 3 * CPL * kThreads;
     const int o_cols = o_vals + static_cast<int>(sizeof(VT)) * tile_slots;
     const int o_coff = o_cols + 4 * tile_slots;
     const int o_cw = o_coff + 4 * (cpt + 1);
@@ -116,18 +166,21 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
 #define CHEBFD_SCW(b) reinterpret_cast<int32_t *>(smem + o_cw + (b) * buf_bytes)
 
     const int tid = threadIdx.x;
-    const int j = tid % NB;
-    const int rr = tid / NB;
+    const int j = tid % LPR;
+    const int jc = j * CPL;                    // first column of this lane
+    const int rr = tid / LPR;
 
     if (a.part_in != nullptr) reduce_prev<NB>(a, sred);
 
-    const VT *__restrict__ P = static_cast<const VT *>(a.P);
+    const T *__restrict__ P = static_cast<const T *>(a.P);   // interleaved re, im
     const VT *__restrict__ gval = static_cast<const VT *>(a.val);
     const int32_t *__restrict__ gcol = a.col;
     const T alpha = static_cast<T>(a.alpha), beta = static_cast<T>(a.beta);
     const T g0 = static_cast<T>(a.g0), g1 = static_cast<T>(a.g1), g2 = static_cast<T>(a.g2);
 
-    double e_re = 0.0, e_im = 0.0, nu = 0.0;
+    double e_re[CPL], e_im[CPL], nu[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) e_re[c] = e_im[c] = nu[c] = 0.0;
 
     // tile range of this workgroup: each XCD sweeps one contiguous eighth
     const int G = gridDim.x, w = blockIdx.x;
@@ -217,15 +270,19 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
             const int cl = r >> a.log2C;
             const int base = (uw > 0 ? cl * a.C * uw : scoffb[cl]) + (r & (a.C - 1));
             const int wdt = uw > 0 ? uw : scwb[cl];
-            const int64_t e = i * NB + j;
+            const int64_t e = 2 * (i * NB + jc);   // scalar offset of the lane's first column
 
             // row streams (U_i is also gathered by neighbours: cached; W, Y: streamed)
-            const VT up = P[e];
-            VT o = {T(0), T(0)}, yv = {T(0), T(0)};
-            if constexpr (MODE != kModeFirst) o = ld_nt(static_cast<const VT *>(a.O) + e);
-            if constexpr (MODE == kModeStep) yv = ld_nt(static_cast<const VT *>(a.Y) + e);
+            const PK up = load_pack<T, CPL, false>(P + e);
+            PK o, yv;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) o.re[c] = o.im[c] = yv.re[c] = yv.im[c] = T(0);
+            if constexpr (MODE != kModeFirst) o = load_pack<T, CPL, true>(static_cast<const T *>(a.O) + e);
+            if constexpr (MODE == kModeStep) yv = load_pack<T, CPL, true>(static_cast<const T *>(a.Y) + e);
 
-            T acc_re = 0, acc_im = 0;
+            T acc_re[CPL], acc_im[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc_re[c] = acc_im[c] = T(0);
             if (wdt <= MAXW) {
                 // Branch-free: slots past the row's width gather the row's own
                 // entry and get coefficient 0; when every chunk holds exactly
@@ -241,59 +298,79 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
                     const int c = sc[sidx[k]];
                     cc[k] = (full || k < wdt) ? c : static_cast<int>(i);
                 }
-                VT u[MAXW];
+                PK u[MAXW];
 #pragma unroll
-                for (int k = 0; k < MAXW; ++k) u[k] = P[(int64_t)cc[k] * NB + j];
+                for (int k = 0; k < MAXW; ++k) u[k] = load_pack<T, CPL, false>(P + 2 * ((int64_t)cc[k] * NB + jc));
 #pragma unroll
                 for (int k = 0; k < MAXW; ++k) {
                     VT h = sv[sidx[k]];
                     if (!(full || k < wdt)) h = VT{T(0), T(0)};
-                    acc_re = fma(h.x, u[k].x, acc_re);
-                    acc_re = fma(-h.y, u[k].y, acc_re);
-                    acc_im = fma(h.x, u[k].y, acc_im);
-                    acc_im = fma(h.y, u[k].x, acc_im);
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        acc_re[c] = fma(h.x, u[k].re[c], acc_re[c]);
+                        acc_re[c] = fma(-h.y, u[k].im[c], acc_re[c]);
+                        acc_im[c] = fma(h.x, u[k].im[c], acc_im[c]);
+                        acc_im[c] = fma(h.y, u[k].re[c], acc_im[c]);
+                    }
                 }
             } else {
                 for (int k = 0; k < wdt; ++k) {
-                    const int c = sc[base + k * a.C];
+                    const int col = sc[base + k * a.C];
                     const VT h = sv[base + k * a.C];
-                    const VT uu = P[(int64_t)c * NB + j];
-                    acc_re = fma(h.x, uu.x, acc_re);
-                    acc_re = fma(-h.y, uu.y, acc_re);
-                    acc_im = fma(h.x, uu.y, acc_im);
-                    acc_im = fma(h.y, uu.x, acc_im);
-                }
-            }
-
-            const T hu_re = fma(alpha, acc_re, beta * up.x);
-            const T hu_im = fma(alpha, acc_im, beta * up.y);
-            VT nw;
-            if constexpr (MODE == kModeFirst) {
-                nw = VT{hu_re, hu_im};
-                st_nt(static_cast<VT *>(a.N) + e, nw);
-            } else {
-                nw.x = fma(T(2), hu_re, -o.x);
-                nw.y = fma(T(2), hu_im, -o.y);
-                if constexpr (MODE == kModeSecond) {
-                    st_nt(static_cast<VT *>(a.N) + e, nw);
-                    VT y;
-                    y.x = fma(g0, o.x, fma(g1, up.x, g2 * nw.x));
-                    y.y = fma(g0, o.y, fma(g1, up.y, g2 * nw.y));
-                    st_nt(static_cast<VT *>(a.Y) + e, y);  // Y aliases O: row i's entry is read only here
-                } else {
-                    st_nt(static_cast<VT *>(a.O) + e, nw);
-                    if constexpr (MODE == kModeStep) {
-                        VT y;
-                        y.x = fma(g2, nw.x, yv.x);
-                        y.y = fma(g2, nw.y, yv.y);
-                        st_nt(static_cast<VT *>(a.Y) + e, y);
+                    const PK uu = load_pack<T, CPL, false>(P + 2 * ((int64_t)col * NB + jc));
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        acc_re[c] = fma(h.x, uu.re[c], acc_re[c]);
+                        acc_re[c] = fma(-h.y, uu.im[c], acc_re[c]);
+                        acc_im[c] = fma(h.x, uu.im[c], acc_im[c]);
+                        acc_im[c] = fma(h.y, uu.re[c], acc_im[c]);
                     }
                 }
             }
-            const double nr = nw.x, ni = nw.y, ur = up.x, ui = up.y;
-            e_re = fma(nr, ur, fma(ni, ui, e_re));
-            e_im = fma(nr, ui, fma(-ni, ur, e_im));
-            nu = fma(ur, ur, fma(ui, ui, nu));
+
+            PK nw;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const T hu_re = fma(alpha, acc_re[c], beta * up.re[c]);
+                const T hu_im = fma(alpha, acc_im[c], beta * up.im[c]);
+                if constexpr (MODE == kModeFirst) {
+                    nw.re[c] = hu_re;
+                    nw.im[c] = hu_im;
+                } else {
+                    nw.re[c] = fma(T(2), hu_re, -o.re[c]);
+                    nw.im[c] = fma(T(2), hu_im, -o.im[c]);
+                }
+            }
+            if constexpr (MODE == kModeFirst) {
+                store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
+            } else if constexpr (MODE == kModeSecond) {
+                store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
+                PK y;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    y.re[c] = fma(g0, o.re[c], fma(g1, up.re[c], g2 * nw.re[c]));
+                    y.im[c] = fma(g0, o.im[c], fma(g1, up.im[c], g2 * nw.im[c]));
+                }
+                store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, y);  // Y aliases O: row i's entry is read only here
+            } else {
+                store_pack_nt<T, CPL>(static_cast<T *>(a.O) + e, nw);
+                if constexpr (MODE == kModeStep) {
+                    PK y;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        y.re[c] = fma(g2, nw.re[c], yv.re[c]);
+                        y.im[c] = fma(g2, nw.im[c], yv.im[c]);
+                    }
+                    store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, y);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const double nr = nw.re[c], ni = nw.im[c], ur = up.re[c], ui = up.im[c];
+                e_re[c] = fma(nr, ur, fma(ni, ui, e_re[c]));
+                e_im[c] = fma(nr, ui, fma(-ni, ur, e_im[c]));
+                nu[c] = fma(ur, ur, fma(ui, ui, nu[c]));
+            }
           }
           // The next tile's slots go to the idle buffer after the first
           // sub-pass: their loads have landed by then, and the wait for them
@@ -305,17 +382,22 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
         __syncthreads();
     }
 
-    // workgroup reduction over the ROWS lanes of each column, fixed order
-    sred[tid] = e_re;
-    sred[kThreads + tid] = e_im;
-    sred[2 * kThreads + tid] = nu;
+    // workgroup reduction over the ROWS lanes of each column, fixed order;
+    // sred[(component * CPL + c) * kThreads + lane]
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        sred[(0 * CPL + c) * kThreads + tid] = e_re[c];
+        sred[(1 * CPL + c) * kThreads + tid] = e_im[c];
+        sred[(2 * CPL + c) * kThreads + tid] = nu[c];
+    }
     __syncthreads();
     if (tid < NB) {
+        const int lj = tid / CPL, c = tid % CPL;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int q = 0; q < ROWS; ++q) {
-            s0 += sred[q * NB + tid];
-            s1 += sred[kThreads + q * NB + tid];
-            s2 += sred[2 * kThreads + q * NB + tid];
+            s0 += sred[(0 * CPL + c) * kThreads + q * LPR + lj];
+            s1 += sred[(1 * CPL + c) * kThreads + q * LPR + lj];
+            s2 += sred[(2 * CPL + c) * kThreads + q * LPR + lj];
         }
         a.part_out[(int64_t)(0 * NB + tid) * G + w] = s0;
         a.part_out[(int64_t)(1 * NB + tid) * G + w] = s1;
@@ -399,17 +481,18 @@ int occ_lds_nb(int nb, int maxw, size_t lds) {
 
 bool lds_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, LdsGeometry *g) {
     if (H->max_width > kMaxTileWidth || H->C > 32) return false;
-    const int rows = kThreads / nb;
+    const int cpl = (prec == CHEBFD_PREC_MIXED && nb >= 2) ? 2 : 1;   // cols_per_lane<T, NB>()
+    const int rows = kThreads * cpl / nb;
     g->tile_rows = rows > H->C ? rows : H->C;
     g->maxw = H->max_width <= 13 ? 13 : kMaxTileWidth;
     const int64_t slots = (int64_t)H->max_width * g->tile_rows;
-    if (slots > (int64_t)lds_prefetch_slots(nb) * kThreads) return false;
+    if (slots > (int64_t)lds_prefetch_slots(rows) * kThreads) return false;
     g->tile_slots = static_cast<int>(slots < 1 ? 1 : slots);
     const int cpt = g->tile_rows / H->C;
     const size_t vb = prec == CHEBFD_PREC_FP64 ? 16 : 8;
     size_t per_buf = vb * g->tile_slots + 4 * g->tile_slots + 4 * (2 * cpt + 1);
     per_buf = (per_buf + 15) / 16 * 16;
-    g->lds_bytes = sizeof(double) * 3 * kThreads + 2 * per_buf;
+    g->lds_bytes = sizeof(double) * 3 * cpl * kThreads + 2 * per_buf;
     g->ntiles = (H->n + g->tile_rows - 1) / g->tile_rows;
     const int occ = prec == CHEBFD_PREC_FP64 ? occ_lds_nb<double>(nb, g->maxw, g->lds_bytes)
                                              : occ_lds_nb<float>(nb, g->maxw, g->lds_bytes);
