@@ -137,12 +137,39 @@ def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target, order, which="
         print(f"# solve {name}: {dt:.2f} s, status {r.status}, {st.iterations} iterations, "
               f"{nf} pairs", file=sys.stderr, flush=True)
         del M
+    if which == "both":
+        # mixed precision with the trained predictor's (n_p, n_s) for this matrix and interval
+        from paper_1803_02156_amd import predictor as PR
+        if os.path.exists(PR.DEFAULT_WEIGHTS):
+            pred = PR.load(PR.DEFAULT_WEIGHTS)
+            f, cnt, _, _ = P.chebfd_features(M64, -delta, delta, 7)
+            lp, ls = PR.choose(pred, f, cnt, pred["kappa"])
+            ls = max(n_b, ls // n_b * n_b)
+            M = P.chebfd_matrix_build(*H, prec=1, order=order)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = P.chebfd_solve(M, M64, -delta, delta, ls, lp, n_b, seed=43, max_iter=12, want_vectors=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            nf = r.n_found
+            out["mixed_learned"] = {"seconds": round(dt, 3), "status": r.status, "iterations": r.stats.iterations,
+                                    "n_found": nf, "n_p": lp, "n_s": ls,
+                                    "max_resid": float(np.max(r.resid[:nf])) if nf else None}
+            print(f"# solve mixed + learned (n_p {lp}, n_s {ls}): {dt:.2f} s, status {r.status}, "
+                  f"{r.stats.iterations} iterations, {nf} pairs", file=sys.stderr, flush=True)
+            del M
     if len(runs) == 2:
         a, b = runs["fp64"], runs["mixed"]
         if a.n_found == b.n_found and a.n_found > 0:
             out["mixed"]["max_abs_dtheta_vs_fp64"] = float(np.max(np.abs(np.sort(a.theta[:a.n_found]) -
                                                                           np.sort(b.theta[:b.n_found]))))
         out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+        ml = out.get("mixed_learned")
+        if ml is not None:
+            ok = ml["status"] == 0 and ml["n_found"] >= a.n_found
+            ml["converged_all_pairs"] = ok
+            # a speedup only for a run that found every pair the FP64 run found
+            out["speedup_mixed_learned_vs_fp64"] = round(out["fp64"]["seconds"] / ml["seconds"], 3) if ok else None
     return out
 
 
