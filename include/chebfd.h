@@ -325,7 +325,9 @@ typedef struct chebfd_predictor {
  * Features of (H, [lam_L, lam_R]): Gershgorin scaling (alpha, beta), the
  * CHEBFD_FEATURE_MOMENTS averaged moments of chebfd_kpm_moments with
  * CHEBFD_FEATURE_R vectors from `seed`, then a~ = alpha lam_L + beta and
- * b~ = alpha lam_R + beta: h_features[258] (FP32, host).  *count_est: the
+ * b~ = alpha lam_R + beta: h_features[258] (FP32, host), except that slot 0
+ * (mu~_0, which is 1 by construction) holds log10(n) / 8: the moments are per
+ * row and the network also needs the size.  *count_est: the
  * eigenvalue count estimate n sum_m g_m c_m mu~_m over the same moments (window
  * coefficients of [a~, b~] and Jackson damping for 256 terms).  Synchronises.
  * CHEBFD_EINTERVAL unless -1 < a~ < b~ < 1.

@@ -59,6 +59,9 @@ int chebfd_features(const chebfd_matrix *H, double lam_L, double lam_R, uint64_t
         acc += gc[m] * mu[m];
         h_features[m] = (float)mu[m];
     }
+    // mu~_0 is 1 by construction; its slot carries the matrix size instead, which
+    // sets the eigenvalue spacing the filter must resolve (the moments are per row)
+    h_features[0] = (float)(std::log10((double)H->n) / 8.0);
     h_features[CHEBFD_FEATURE_MOMENTS] = (float)(al * lam_L + be);
     h_features[CHEBFD_FEATURE_MOMENTS + 1] = (float)(al * lam_R + be);
     *count_est = (double)H->n * acc;

@@ -13,7 +13,9 @@ spectrum (Sect. 2).  This module turns that picture into the two parameters:
   (``chebfd_mlp_grad`` / ``chebfd_mlp_adam``) on runs of the method itself.
 
 Labels: for each instance a small grid of (n_p, n_s) around the heuristic is
-solved, and the label is the grid point with the least deterministic work
+solved (or, adaptively, n_p is doubled from the heuristic's until the solver
+finds pairs, then one more doubling and one wider subspace are tried), and the
+label is the run with the least deterministic work
 ``iters (n_p n_s nnz + c_orth n n_s^2)`` among the runs that converged with the
 full eigenvalue count; the network regresses the standardised
 (log n_p, log n_s) of that point.
@@ -109,8 +111,10 @@ def grid(heur_np: int, heur_ns: int):
     return [(a, b) for a in nps for b in nss]
 
 
-def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, count_range=None, log=print):
-    """Features, heuristic choice, grid runs and labels of `count` instances."""
+def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, count_range=None, log=print,
+                adaptive: bool = False, start_np: int = 50, out: str | None = None):
+    """Features, heuristic choice, grid runs and labels of `count` instances
+    (written to `out` after every instance when given)."""
     rng = np.random.default_rng(seed)
     rows = []
     for k in range(count):
@@ -123,20 +127,52 @@ def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, c
         a, b = f[256], f[257]
         hp, hs = P.chebfd_choose_params(float(a), float(b), cnt, N_B, kappa=kappa)
         results = []
-        for n_p, n_s in grid(hp, hs):
+
+        def solve(n_p, n_s):
             r, dt = run(M, inst, n_p, n_s)
             results.append(dict(n_p=n_p, n_s=n_s, status=r.status, iters=r.stats.iterations,
                                 n_found=r.n_found, seconds=dt,
                                 work=work_units(n, nnz, n_p, n_s, r.stats.iterations)))
+            log(f"#   run n_p {n_p} n_s {n_s}: status {r.status}, {r.stats.iterations} it, "
+                f"{r.n_found} pairs, {dt:.2f} s")
+            return r.status == 0 and r.n_found > 0
+        if adaptive:
+            # double n_p from the heuristic's until a run finds pairs, then one more
+            # doubling and one wider subspace at that degree
+            n_p = max(hp, start_np)
+            while n_p <= _abi.NP_MAX:
+                if solve(n_p, hs):
+                    if 2 * n_p <= _abi.NP_MAX:
+                        solve(2 * n_p, hs)
+                    solve(n_p, min(512, hs + N_B))
+                    break
+                n_p *= 2
+        else:
+            for n_p, n_s in grid(hp, hs):
+                solve(n_p, n_s)
         full = max(x["n_found"] for x in results)
         ok = [x for x in results if x["status"] == 0 and x["n_found"] == full]
-        best = min(ok, key=lambda x: x["work"]) if ok else None
+        # no label where no run found a pair: the grid then says nothing about (n_p, n_s)
+        best = min(ok, key=lambda x: x["work"]) if ok and full > 0 else None
         rows.append(dict(inst=inst.__dict__, n=n, nnz=nnz, features=f.tolist(), count_est=cnt,
                          heuristic=(hp, hs), runs=results, full_count=full,
                          label=None if best is None else (best["n_p"], best["n_s"])))
         log(f"# corpus {k + 1}/{count}: dims {inst.dims} n={n} count~{cnt:.1f} found {full} "
             f"heur ({hp},{hs}) label {rows[-1]['label']}")
+        if out:
+            with open(out + ".tmp", "w") as f:
+                json.dump(rows, f)
+            os.replace(out + ".tmp", out)
     return rows
+
+
+def features_of(row: dict) -> np.ndarray:
+    """The 258 network inputs of a corpus row.  Slot 0 holds log10(n) / 8, as
+    chebfd_features writes it (the normalised moment mu~_0 it replaces is 1 by
+    construction); rows stored before that convention get it from their n."""
+    f = np.asarray(row["features"], dtype=np.float32).copy()
+    f[0] = np.float32(np.log10(float(row["n"])) / 8.0)
+    return f
 
 
 def standardise(labels: np.ndarray):
@@ -206,7 +242,7 @@ def evaluate(pred: dict, corpus: list, kappa: float, log=print):
     for k, row in enumerate(corpus):
         inst = Instance(**{**row["inst"], "dims": tuple(row["inst"]["dims"])})
         H, M = build(inst)
-        f = np.asarray(row["features"], dtype=np.float32)
+        f = features_of(row)
         res = {}
         for name, pr in (("heuristic", None), ("mlp", pred)):
             n_p, n_s = choose(pr, f, row["count_est"], kappa)
@@ -269,6 +305,9 @@ def main(argv=None):
     c.add_argument("--kappa", type=float, required=True)
     c.add_argument("--counts", type=float, nargs=2, default=None,
                    help="size each interval for an eigenvalue count drawn from this range")
+    c.add_argument("--adaptive", action="store_true",
+                   help="label by doubling n_p from the heuristic's until pairs are found")
+    c.add_argument("--start-np", type=int, default=50, help="adaptive labels start at max(heuristic, this)")
     c.add_argument("--out", required=True)
     k = sub.add_parser("kappa")
     k.add_argument("--dims", type=int, nargs=3, default=(16, 16, 8))
@@ -289,13 +328,12 @@ def main(argv=None):
         inst = Instance(dims=tuple(a.dims), m=1.0, W=1.0, half_width=0.05, seed=1001)
         log(json.dumps({"kappa": calibrate_kappa(inst, 32, log=log)}))
     elif a.cmd == "corpus":
-        rows = make_corpus(a.count, a.seed, a.ext[0], a.ext[1], a.kappa,
-                           count_range=None if a.counts is None else tuple(a.counts), log=log)
-        with open(a.out, "w") as f:
-            json.dump(rows, f)
+        make_corpus(a.count, a.seed, a.ext[0], a.ext[1], a.kappa,
+                    count_range=None if a.counts is None else tuple(a.counts), log=log,
+                    adaptive=a.adaptive, start_np=a.start_np, out=a.out)
     elif a.cmd == "train":
-        rows = [r for p in a.corpus for r in json.load(open(p)) if r["label"] is not None]
-        X = np.array([r["features"] for r in rows], dtype=np.float32)
+        rows = [r for p in a.corpus for r in json.load(open(p)) if r["label"] is not None and r["full_count"] > 0]
+        X = np.array([features_of(r) for r in rows], dtype=np.float32)
         T, mean, std = standardise(np.array([r["label"] for r in rows], dtype=np.float64))
         params = train(X, T, steps=a.steps, log=log)
         save(a.out, params, mean, std, a.kappa, {"train_instances": len(rows), "steps": a.steps,

@@ -111,7 +111,8 @@ def test_features_match_oracle(P, prec):
     _, eta, nu = O.chebyshev_filter(H, ral, rbe, np.zeros(129), X, 16)
     mu = np.real(np.sum(O.kpm_moments(eta, nu), axis=1)) / (n * 16)
     tol = 1e-6 if prec == 0 else 2e-4          # features are stored in FP32
-    assert np.max(np.abs(f[:256] - mu)) < tol
+    assert np.max(np.abs(f[1:256] - mu[1:])) < tol
+    assert abs(mu[0] - 1.0) < 1e-12 and f[0] == np.float32(np.log10(n) / 8.0)   # slot 0: the size
     assert abs(f[256] - (ral * -0.3 + rbe)) < 1e-7 and abs(f[257] - (ral * 0.3 + rbe)) < 1e-7
     ref_cnt = O.count_estimate(O.kpm_moments(eta, nu), n, ral * -0.3 + rbe, ral * 0.3 + rbe)
     assert abs(cnt - ref_cnt) < (1e-9 if prec == 0 else 1e-2) * max(1.0, abs(ref_cnt))

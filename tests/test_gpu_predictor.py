@@ -26,7 +26,7 @@ def test_network_output_matches_oracle_forward(PR):
     import oracle.mlp as OM
     pred = PR.load(os.path.join(DATA, "predictor.npz"))
     rows = json.load(open(os.path.join(DATA, "corpus_eval.json")))
-    X = np.array([r["features"] for r in rows], dtype=np.float32)
+    X = np.array([PR.features_of(r) for r in rows], dtype=np.float32)
     y = PR.predict(pred["params"], X)
     ref, _ = OM.forward(pred["params"].astype(np.float64), X.astype(np.float64))
     assert np.max(np.abs(y - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
