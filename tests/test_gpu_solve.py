@@ -238,3 +238,25 @@ def test_solve_mixed_matches_fp64_on_disordered_lattice(P):
     assert np.max(np.abs(np.sort(r.theta[:nf]) - ref)) < 1e-12
     Z = r.Z.cpu().numpy()[:, :nf]
     assert np.max(np.linalg.norm(A @ Z - Z * r.theta[None, :nf], axis=0) / np.linalg.norm(Z, axis=0)) <= 1e-7
+
+
+def test_solve_start_block_and_bounds_arguments(P):
+    """d_x0 = the same random-phase block the device draws from the seed gives the
+    same Ritz values; caller spectral bounds equal to Gershgorin's give the same
+    result; an interval outside the bounds is rejected (EINTERVAL)."""
+    H = topi_csr(4, 4, 3, m=1.0, W=2.0, seed=1001)
+    n = len(H[0]) - 1
+    M = P.chebfd_matrix_build(*H, prec=0)
+    r1 = P.chebfd_solve(M, M, -0.8, 0.8, 32, 150, 16, seed=43)
+    X0 = random_phase_block(n, 32, 43)
+    x0 = torch.empty((32, n), dtype=torch.complex128, device="cuda")
+    x0.copy_(torch.from_numpy(np.ascontiguousarray(X0.T)))
+    r2 = P.chebfd_solve(M, M, -0.8, 0.8, 32, 150, 16, seed=43, x0=x0.T)
+    assert r1.status == r2.status == 0 and r1.n_found == r2.n_found
+    assert np.array_equal(r1.theta[:r1.n_found], r2.theta[:r2.n_found])
+    lo, hi = P.chebfd_bounds(M)
+    r3 = P.chebfd_solve(M, M, -0.8, 0.8, 32, 150, 16, seed=43, spec_bounds=(lo, hi), want_vectors=False)
+    assert r3.Z is None and np.array_equal(r1.theta[:r1.n_found], r3.theta[:r3.n_found])
+    with pytest.raises(P.ChebfdError) as e:
+        P.chebfd_solve(M, M, hi + 1.0, hi + 2.0, 32, 150, 16)
+    assert e.value.code == -4
