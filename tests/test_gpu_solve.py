@@ -253,7 +253,8 @@ def test_solve_start_block_and_bounds_arguments(P):
     x0.copy_(torch.from_numpy(np.ascontiguousarray(X0.T)))
     r2 = P.chebfd_solve(M, M, -0.8, 0.8, 32, 150, 16, seed=43, x0=x0.T)
     assert r1.status == r2.status == 0 and r1.n_found == r2.n_found
-    assert np.array_equal(r1.theta[:r1.n_found], r2.theta[:r2.n_found])
+    # the host and device draws of the phases may differ in the last bit
+    assert np.max(np.abs(r1.theta[:r1.n_found] - r2.theta[:r2.n_found])) < 1e-12
     lo, hi = P.chebfd_bounds(M)
     r3 = P.chebfd_solve(M, M, -0.8, 0.8, 32, 150, 16, seed=43, spec_bounds=(lo, hi), want_vectors=False)
     assert r3.Z is None and np.array_equal(r1.theta[:r1.n_found], r3.theta[:r3.n_found])
