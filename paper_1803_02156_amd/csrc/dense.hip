@@ -79,28 +79,45 @@ __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int prec_a, int
     const int wv = threadIdx.x >> 6;
     const int wa = (wv & 1) * 32, wb = (wv >> 1) * 32;  // wave's 32 x 32 sub-tile
 
-    d4v acc[2][2][4];
+    // two accumulators per 16 x 16 tile: real and imaginary part of the sum
+    d4v acc[2][2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < 2; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t rb = r0; rb < r1; rb += kGK) {
-        // stage kGK rows x 64 columns of A and of B (zero outside the matrices)
-        for (int t = threadIdx.x; t < kGK * kGT; t += kT) {
+    // Stages of kGK rows x 64 columns of A and of B (zero outside the matrices):
+    // the next stage's global loads are issued before the current stage's
+    // products, so their latency hides behind the matrix-core work.
+    constexpr int kPer = kGK * kGT / kT;   // elements per thread and matrix
+    double2 ra[kPer], rb2[kPer];
+    auto fetch = [&](int64_t rbase) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int t = threadIdx.x + q * kT;
             const int rr = t / kGT, cc = t % kGT;
-            const int64_t i = rb + rr;
+            const int64_t i = rbase + rr;
             double2 va = {0.0, 0.0}, vb = {0.0, 0.0};
             if (i < r1) {
                 if (a0 + cc < m1) va = load_c(A, prec_a, blocked_index(n, nb_a, i, a0 + cc));
                 if (b0 + cc < m2) vb = load_c(B, prec_b, blocked_index(n, nb_b, i, b0 + cc));
             }
-            sa[rr][cc] = va;
-            sb[rr][cc] = vb;
+            ra[q] = va;
+            rb2[q] = vb;
+        }
+    };
+    if (r0 < r1) fetch(r0);
+    for (int64_t rb = r0; rb < r1; rb += kGK) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int t = threadIdx.x + q * kT;
+            sa[t / kGT][t % kGT] = ra[q];
+            sb[t / kGT][t % kGT] = rb2[q];
         }
         __syncthreads();
+        if (rb + kGK < r1) fetch(rb + kGK);
 #pragma unroll
         for (int k0 = 0; k0 < kGK; k0 += 4) {
             const int kk = k0 + lane / 16;
@@ -112,9 +129,9 @@ __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int prec_a, int
                     const double2 bv = sb[kk][wb + 16 * y + lane % 16];
                     // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
                     acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, acc[x][y][0], 0, 0, 0);
-                    acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, acc[x][y][1], 0, 0, 0);
-                    acc[x][y][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, acc[x][y][2], 0, 0, 0);
-                    acc[x][y][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, acc[x][y][3], 0, 0, 0);
+                    acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, acc[x][y][0], 0, 0, 0);
+                    acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, acc[x][y][1], 0, 0, 0);
+                    acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.x, acc[x][y][1], 0, 0, 0);
                 }
             }
         }
@@ -132,8 +149,8 @@ __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int prec_a, int
                 const int ra = wa + 16 * x + lane / 16 + 4 * r;  // row of S (column of A)
                 const int cb = wb + 16 * y + lane % 16;            // column of S
                 double2 v;
-                v.x = acc[x][y][0][r] + acc[x][y][1][r];
-                v.y = acc[x][y][2][r] - acc[x][y][3][r];
+                v.x = acc[x][y][0][r];
+                v.y = acc[x][y][1][r];
                 out[(int64_t)cb * kGT + ra] = v;
             }
 }
@@ -176,13 +193,14 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int prec_a, i
     const int wi = (wv & 1) * 32, wc = (wv >> 1) * 32;
     const double2 *Mc = reinterpret_cast<const double2 *>(M);
 
-    d4v acc[2][2][4];
+    // two accumulators per 16 x 16 tile: real and imaginary part of the sum
+    d4v acc[2][2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < 2; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
 
     for (int k0 = 0; k0 < m1; k0 += kGK) {
         for (int t = threadIdx.x; t < kGT * kGK; t += kT) {
@@ -210,9 +228,9 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int prec_a, i
                     const double2 mv = sm[kk][wc + 16 * y + lane % 16];
                     // a m = (ar mr - ai mi) + i (ar mi + ai mr)
                     acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, mv.x, acc[x][y][0], 0, 0, 0);
-                    acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, mv.y, acc[x][y][1], 0, 0, 0);
-                    acc[x][y][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, mv.y, acc[x][y][2], 0, 0, 0);
-                    acc[x][y][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, mv.x, acc[x][y][3], 0, 0, 0);
+                    acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, mv.y, acc[x][y][0], 0, 0, 0);
+                    acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, mv.y, acc[x][y][1], 0, 0, 0);
+                    acc[x][y][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, mv.x, acc[x][y][1], 0, 0, 0);
                 }
             }
         }
@@ -228,8 +246,8 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int prec_a, i
                 const int c = c0 + wc + 16 * y + lane % 16;
                 if (i < n && c < m2) {
                     double2 v;
-                    v.x = acc[x][y][0][r] - acc[x][y][1][r];
-                    v.y = acc[x][y][2][r] + acc[x][y][3][r];
+                    v.x = acc[x][y][0][r];
+                    v.y = acc[x][y][1][r];
                     store_c(Z, prec_z, blocked_index(n, nb_z, i, c), v);
                 }
             }
