@@ -56,25 +56,31 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SRC = os.path.join(HERE, "paper_1803_02156_amd", "csrc", "filter_lds.hip")
+# fused-step kernels (chebfd_step_kernel kinds): short name, source file
+STEP_KERNELS = {0: ("cheb_lds", "filter_lds.hip"), 1: ("cheb_row", "filter_rows.hip"),
+                2: ("cheb_multirow", "filter.hip"), 3: ("cheb_win", "filter_win.hip")}
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_source_hash(kind: int) -> str:
+    """Hash of the step kernel's source and the pack header it includes."""
+    h = hashlib.sha256()
+    for name in (STEP_KERNELS[kind][1], "step_io.h"):
+        with open(os.path.join(HERE, "paper_1803_02156_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def counter_traffic(prec: int, n_b: int, lattice: str, order: str):
+def counter_traffic(kind: int, prec: int, n_b: int, lattice: str, order: str):
     """HBM bytes per fused-step launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, if it was taken on the current kernel source; else None."""
-    name = (f"traffic_cheb_lds_step_topi{lattice.replace('x', '-')}_{'fp64' if prec == 0 else 'mixed'}"
-            f"_nb{n_b}_{order}.json")
+    name = (f"traffic_{STEP_KERNELS[kind][0]}_step_topi{lattice.replace('x', '-')}_"
+            f"{'fp64' if prec == 0 else 'mixed'}_nb{n_b}_{order}.json")
     path = os.path.join(HERE, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(kind):
         return None
     return t["hbm_bytes_per_launch"]
 
@@ -286,7 +292,8 @@ def main():
     avg_launch_s = filt_ms * 1e-3 / ((n_s // n_b) * n_p)
     r, w = traffic.step_bytes(n, nnz, n_b, prec)
     achieved = (r + w) / avg_launch_s / 1e9
-    hbm = counter_traffic(prec, n_b, args.lattice, args.order)
+    kind = P.chebfd_step_kernel(M, n_b)
+    hbm = counter_traffic(kind, prec, n_b, args.lattice, args.order)
     del opw
     # the orthogonalisation's Gram product Y^H Y over the whole search block (FP64 MFMA)
     P.chebfd_gram(xy.view(n_s // n_b, n, n_b), xy.view(n_s // n_b, n, n_b))
@@ -354,10 +361,10 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": hbm,
-            "kernel": f"cheb_lds_kernel<{'double' if prec == 0 else 'float'},{n_b},kModeStep>",
+            "kernel": f"{STEP_KERNELS[kind][0]}_kernel<{'double' if prec == 0 else 'float'},{n_b},kModeStep>",
             "bytes_per_launch": r + w, "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "fused_step_alone_us": round(op_alone_s * 1e6, 3),
-            "kernel_source_sha256_16": kernel_source_hash(),
+            "kernel_source_sha256_16": kernel_source_hash(kind),
         },
         "gram": {"kernel": "gram_kernel (FP64 MFMA 16x16x4)", "shape": f"{n} x {n_s} x {n_s} complex",
                  "ms": round(gram_ms, 3), "tflops": round(gram_tflops, 2),

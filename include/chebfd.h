@@ -70,6 +70,9 @@ typedef struct chebfd_matrix {
     int32_t max_width;          /* longest row */
     int32_t identity_perm;      /* 1 if the permutation is the identity */
     int32_t uniform_width;      /* slots per row of every chunk if all chunks are equally wide, else 0 */
+    int32_t window_local[2];    /* stored entries per 1000 whose column lies in the row window of its
+                                   tile (tiles of 32 and 64 rows, window 3 tiles either side); the
+                                   filter gathers such entries from a copy of U staged in LDS */
     const int64_t *chunk_off;   /* [n_chunks + 1] first slot of each chunk */
     const int32_t *chunk_width; /* [n_chunks] slots per row in the chunk */
     const int32_t *col;         /* [slots] permuted column index */
@@ -163,6 +166,26 @@ int chebfd_unpack(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec,
  * Buffers must be 256-byte aligned and must not overlap.
  */
 int chebfd_filter_query(const chebfd_matrix *H, int32_t n_b, size_t *work_bytes);
+
+/*
+ * The fused-step kernel that chebfd_filter, chebfd_op, chebfd_spmmv and the
+ * moment calls launch for H and n_b (all compute the same step; they differ in
+ * what they stage in LDS):
+ *   CHEBFD_KERNEL_WINDOW   one workgroup per CU sweeps a contiguous row range and
+ *                          gathers U from a window of U rows staged in LDS (FP64
+ *                          n_b = 32 and c64 n_b = 64; C = 32; rows of at most 13
+ *                          entries; window_local[] >= 700 for the tile height:
+ *                          32 rows for both)
+ *   CHEBFD_KERNEL_LDS      the tile's matrix slots staged in LDS, U gathered from
+ *                          memory (rows of up to 16 entries, C <= 32)
+ *   CHEBFD_KERNEL_ROW      one row per wavefront group (n_b >= 32, wider rows)
+ *   CHEBFD_KERNEL_MULTIROW several rows per wavefront (n_b < 32, wider rows)
+ */
+#define CHEBFD_KERNEL_LDS      0
+#define CHEBFD_KERNEL_ROW      1
+#define CHEBFD_KERNEL_MULTIROW 2
+#define CHEBFD_KERNEL_WINDOW   3
+int chebfd_step_kernel(const chebfd_matrix *H, int32_t n_b, int32_t *kind);
 int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
                   int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
                   void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,

@@ -22,7 +22,7 @@ class ChebfdMatrix(ctypes.Structure):
     _fields_ = [
         ("n", i64), ("nnz", i64), ("n_chunks", i64), ("slots", i64),
         ("C", i32), ("sigma", i32), ("prec", i32), ("max_width", i32),
-        ("identity_perm", i32), ("uniform_width", i32),
+        ("identity_perm", i32), ("uniform_width", i32), ("window_local", i32 * 2),
         ("chunk_off", P), ("chunk_width", P), ("col", P), ("val", P),
         ("perm", P), ("iperm", P),
     ]
@@ -67,6 +67,7 @@ SIGNATURES = {
     "chebfd_pack": (ctypes.c_int, [MP, i32, i32, i32, P, P, P]),
     "chebfd_unpack": (ctypes.c_int, [MP, i32, i32, i32, P, P, P]),
     "chebfd_filter_query": (ctypes.c_int, [MP, i32, ctypes.POINTER(sz)]),
+    "chebfd_step_kernel": (ctypes.c_int, [MP, i32, ctypes.POINTER(i32)]),
     "chebfd_filter": (ctypes.c_int, [MP, f64, f64, P, i32, i32, i32, i32, P, P, P, P, P, P, sz, P]),
     "chebfd_op": (ctypes.c_int, [MP, f64, f64, f64, i32, i32, P, P, P, P, sz, P]),
     "chebfd_spmmv": (ctypes.c_int, [MP, f64, f64, i32, i32, P, P, P, sz, P]),

@@ -148,6 +148,17 @@ def chebfd_unpack(H: Matrix, xb: torch.Tensor, prec: int | None = None, out=None
     return out
 
 
+KERNEL_LDS, KERNEL_ROW, KERNEL_MULTIROW, KERNEL_WINDOW = 0, 1, 2, 3
+KERNEL_NAMES = {KERNEL_LDS: "lds", KERNEL_ROW: "row", KERNEL_MULTIROW: "multirow", KERNEL_WINDOW: "window"}
+
+
+def chebfd_step_kernel(H: Matrix, n_b: int) -> int:
+    """Which fused-step kernel the filter calls launch for H and n_b (KERNEL_*)."""
+    k = ctypes.c_int32()
+    check(load().chebfd_step_kernel(H.ref(), n_b, ctypes.byref(k)))
+    return k.value
+
+
 def chebfd_filter_query(H: Matrix, n_b: int) -> int:
     b = ctypes.c_size_t()
     check(load().chebfd_filter_query(H.ref(), n_b, ctypes.byref(b)))

@@ -277,6 +277,21 @@ int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col
     m.uniform_width = p.max_width;
     for (int64_t c = 0; c < p.n_chunks; ++c)
         if (p.width[c] != p.max_width) { m.uniform_width = 0; break; }
+    // locality of the gathers: entries whose column lies within kWinHalo tiles
+    // of their row's tile (tiles of 32 and 64 rows)
+    for (int v = 0; v < 2; ++v) {
+        const int64_t tr = 32 << v;
+        int64_t local = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t t0 = i / tr * tr;
+            const int32_t old = p.perm[i];
+            for (int64_t k = h_rowptr[old]; k < h_rowptr[old + 1]; ++k) {
+                const int64_t q = iperm[h_col[k]];
+                local += (q >= t0 - kWinHalo * tr && q < t0 + (kWinHalo + 1) * tr) ? 1 : 0;
+            }
+        }
+        m.window_local[v] = nnz > 0 ? static_cast<int32_t>(local * 1000 / nnz) : 1000;
+    }
     m.chunk_off = reinterpret_cast<const int64_t *>(base + L.o_off);
     m.chunk_width = reinterpret_cast<const int32_t *>(base + L.o_width);
     m.col = reinterpret_cast<const int32_t *>(base + L.o_col);
@@ -410,22 +425,29 @@ static size_t filter_work_bytes(int nb, int G) {
     return 2 * round_up(sizeof(double) * 3 * nb * (size_t)G, 256);
 }
 
-// Launch geometry of the step kernels.  The LDS-staged kernel is used whenever
-// a tile's slots fit its LDS budget (every matrix with rows up to a few hundred
-// entries); otherwise n_b >= 32 uses the row-per-wavefront kernel and smaller
-// n_b the multi-row kernel.
+// Launch geometry of the step kernels.  The window kernel (U staged in LDS)
+// serves the block widths it has instances for when the row order keeps most
+// gathers within its window; otherwise the LDS-staged kernel (matrix slots in
+// LDS) is used whenever a tile's slots fit its LDS budget (every matrix with
+// rows up to a few hundred entries); otherwise n_b >= 32 uses the
+// row-per-wavefront kernel and smaller n_b the multi-row kernel.
 struct StepGeometry {
-    int kind;           // 0 = LDS-staged, 1 = row per wavefront, 2 = multi-row
+    int kind;           // 0 = LDS-staged, 1 = row per wavefront, 2 = multi-row, 3 = window
     int64_t npass;      // passes (kinds 1, 2)
     int G;
     LdsGeometry lds;
+    WinGeometry win;
 };
 
 static int filter_geometry(const chebfd_matrix *H, int prec, int nb, StepGeometry *g) {
     DeviceProps d;
     int rc = device_props(&d);
     if (rc) return rc;
-    if (lds_geometry(H, prec, nb, d.num_cus, &g->lds)) {
+    if (win_geometry(H, prec, nb, d.num_cus, &g->win)) {
+        g->kind = 3;
+        g->npass = g->win.ntiles;
+        g->G = g->win.G;
+    } else if (lds_geometry(H, prec, nb, d.num_cus, &g->lds)) {
         g->kind = 0;
         g->npass = g->lds.ntiles;
         g->G = g->lds.G;
@@ -449,6 +471,7 @@ static int filter_geometry(const chebfd_matrix *H, int prec, int nb, StepGeometr
 static int launch_any(const chebfd_matrix *H, int prec, int nb, int mode, StepArgs a,
                       const StepGeometry &g, hipStream_t s) {
     a.npass = g.npass;
+    if (g.kind == 3) return launch_win_step(prec, nb, mode, a, g.win, s);
     if (g.kind == 0) return launch_lds_step(prec, nb, mode, a, g.lds, s);
     if (g.kind == 1) return launch_row_step(prec, nb, H->max_width, mode, a, g.G, s);
     return launch_step(prec, nb, mode, a, g.G, s);
@@ -462,6 +485,17 @@ int chebfd_filter_query(const chebfd_matrix *H, int32_t n_b, size_t *work_bytes)
     StepGeometry g;
     if ((rc = filter_geometry(H, H->prec, n_b, &g))) return rc;
     *work_bytes = filter_work_bytes(n_b, g.G);
+    return CHEBFD_OK;
+}
+
+int chebfd_step_kernel(const chebfd_matrix *H, int32_t n_b, int32_t *kind) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(H->prec, n_b))) return rc;
+    CHEBFD_REQUIRE(kind != nullptr, "kind is NULL");
+    StepGeometry g;
+    if ((rc = filter_geometry(H, H->prec, n_b, &g))) return rc;
+    *kind = g.kind;
     return CHEBFD_OK;
 }
 

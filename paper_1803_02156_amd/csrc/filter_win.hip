@@ -1,0 +1,458 @@
+// Fused Chebyshev step with the gathered block staged in LDS (gfx950).
+//
+// Same computation as the other step kernels (Alg. 1 lines 9-12 of the ChebFD
+// paper, and the start launches of lines 4-6): per row i and block column j,
+// W_ij <- 2 ((aH + bI) U)_ij - W_ij, the filtered-block update and the
+// per-column dot products.
+//
+// The sparse product gathers whole row segments of U (NB complex numbers) at
+// the matrix's column indices.  After a locality-preserving row order most of
+// those columns lie close to the row, so one workgroup per CU sweeps a
+// contiguous range of tiles and keeps a window of U in LDS: a ring of
+// kWinBlocks blocks of TR rows (TR = rows of one tile, 16 KB per block).
+// While tile t (rows [t TR, t TR + TR)) is processed the ring holds blocks
+// t - kWinHalo .. t + kWinHalo and receives block t + kWinHalo + 1, which is
+// loaded from HBM once (coalesced, one 16-byte access per thread) and read by
+// the next 2 kWinHalo + 1 tiles.  Gathers inside the window are LDS reads;
+// columns outside it are gathered from global memory as before.  The vector
+// memory pipeline then carries about one U access per row instead of one per
+// stored entry, plus the streams of W and Y (non-temporal) and the matrix
+// slots (staged in LDS per tile, double buffered).
+//
+// Lanes: TR = 1024 * CPL / NB rows per tile; lane t works on columns
+// [CPL (t % LPR), CPL (t % LPR) + CPL) of row t / LPR of the tile.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.h"
+#include "kernels.h"
+#include "step_io.h"
+
+namespace chebfd {
+namespace {
+
+using namespace step_io;
+
+constexpr int kWinThreads = 1024;
+constexpr int kXcdCount = 8;
+constexpr int kWinLdsLimit = 160 * 1024;
+
+template <typename T, int NB>
+struct WinShape {
+    static constexpr int CPL = cols_per_lane<T, NB>();
+    static constexpr int LPR = NB / CPL;               // lanes per row
+    static constexpr int TR = kWinThreads / LPR;       // rows per tile (one per lane group)
+    static constexpr int RB = NB * 2 * sizeof(T);      // bytes of one row of U
+    static constexpr int RING_ROWS = kWinBlocks * TR;  // power of two
+    static constexpr int CPT = TR / 32;                // SELL chunks (C = 32) per tile
+};
+
+template <typename T, int MAXW, int TR>
+struct WinMatBuf {
+    using VT = typename V2<T>::type;
+    static constexpr int SLOTS = TR * MAXW;
+    static constexpr int CPT = TR / 32;
+    static constexpr int O_VALS = 0;
+    static constexpr int O_COLS = O_VALS + SLOTS * static_cast<int>(sizeof(VT));
+    static constexpr int O_COFF = O_COLS + 4 * SLOTS;
+    static constexpr int O_CW = O_COFF + 4 * (CPT + 1);
+    static constexpr int BYTES = (O_CW + 4 * CPT + 15) & ~15;
+};
+
+template <typename T, int NB, int MAXW>
+constexpr int win_lds_bytes() {
+    using S = WinShape<T, NB>;
+    return S::RING_ROWS * S::RB + 2 * WinMatBuf<T, MAXW, S::TR>::BYTES;
+}
+
+template <typename T, int NB>
+constexpr bool win_supported() {
+    using S = WinShape<T, NB>;
+    return S::TR >= 32 && S::TR % 32 == 0 && S::TR * kWinWidth <= kWinThreads &&
+           win_lds_bytes<T, NB, kWinWidth>() <= kWinLdsLimit;
+}
+
+// partials of the previous launch (3 NB columns of G_prev values), fixed order
+template <int NB>
+__device__ void win_reduce_prev(const StepArgs &a, double *sred) {
+    const int tid = threadIdx.x;
+    for (int q = blockIdx.x; q < 3 * NB; q += gridDim.x) {
+        const double *src = a.part_in + (int64_t)q * a.G_prev;
+        double s = 0.0;
+        for (int g = tid; g < a.G_prev; g += kWinThreads) s += src[g];
+        sred[tid] = s;
+        __syncthreads();
+        for (int hh = kWinThreads / 2; hh > 0; hh >>= 1) {
+            if (tid < hh) sred[tid] += sred[tid + hh];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const int comp = q / NB, jj = q % NB;
+            if (comp < 2)
+                a.red_eta[2 * jj + comp] = sred[0];
+            else
+                a.red_nu[jj] = sred[0];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+// LDS layout (dynamic): ring[RING_ROWS][RB] | 2 x { vals[SLOTS], cols[SLOTS], coff[CPT + 1], cw[CPT] }.
+// The ring area also serves the reductions before the first and after the last tile.
+template <typename T, int NB, int MODE, int MAXW, bool UNI>
+__global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64_t ntiles) {
+    using S = WinShape<T, NB>;
+    using MB = WinMatBuf<T, MAXW, S::TR>;
+    using VT = typename V2<T>::type;
+    using PK = Pack<T, S::CPL>;
+    constexpr int CPL = S::CPL, LPR = S::LPR, TR = S::TR, RB = S::RB;
+    constexpr int CPT = S::CPT;
+    constexpr int O_MAT = S::RING_ROWS * RB;
+    static_assert(win_supported<T, NB>(), "tile shape does not fit the window kernel");
+    static_assert(MB::SLOTS <= kWinThreads, "one matrix slot per thread and tile");
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *sred = reinterpret_cast<double *>(smem);
+#define CHEBFD_WV(b) reinterpret_cast<VT *>(smem + O_MAT + (b) * MB::BYTES + MB::O_VALS)
+#define CHEBFD_WC(b) reinterpret_cast<int32_t *>(smem + O_MAT + (b) * MB::BYTES + MB::O_COLS)
+#define CHEBFD_WCOFF(b) reinterpret_cast<int32_t *>(smem + O_MAT + (b) * MB::BYTES + MB::O_COFF)
+#define CHEBFD_WCW(b) reinterpret_cast<int32_t *>(smem + O_MAT + (b) * MB::BYTES + MB::O_CW)
+    // byte offset of row q of U inside the ring, plus this lane's columns
+#define CHEBFD_RING(q) reinterpret_cast<const T *>(smem + ((q) & (S::RING_ROWS - 1)) * RB + lane_off)
+
+    const int tid = threadIdx.x;
+    const int jc = (tid % LPR) * CPL;          // first column of this lane
+    const int rr = tid / LPR;                  // row within the tile
+    const int lane_off = jc * 2 * static_cast<int>(sizeof(T));
+
+    if (a.part_in != nullptr) win_reduce_prev<NB>(a, sred);
+
+    const T *__restrict__ P = static_cast<const T *>(a.P);
+    const VT *__restrict__ gval = static_cast<const VT *>(a.val);
+    const int32_t *__restrict__ gcol = a.col;
+    const T alpha = static_cast<T>(a.alpha), beta = static_cast<T>(a.beta);
+    const T g0 = static_cast<T>(a.g0), g1 = static_cast<T>(a.g1), g2 = static_cast<T>(a.g2);
+    const int64_t nblk = (a.n + TR - 1) / TR;
+
+    double e_re[CPL], e_im[CPL], nu[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) e_re[c] = e_im[c] = nu[c] = 0.0;
+
+    // contiguous tile range of this workgroup; each XCD sweeps one eighth
+    const int G = gridDim.x, w = blockIdx.x;
+    int64_t tb, te;
+    if (G % kXcdCount == 0) {
+        const int x = w % kXcdCount, k = w / kXcdCount, per = G / kXcdCount;
+        const int64_t xb = ntiles * x / kXcdCount, xe = ntiles * (x + 1) / kXcdCount;
+        tb = xb + (xe - xb) * k / per;
+        te = xb + (xe - xb) * (k + 1) / per;
+    } else {
+        tb = ntiles * w / G;
+        te = ntiles * (w + 1) / G;
+    }
+
+    // matrix slots of one tile: one slot per thread (prefetch register, then LDS)
+    const int uw = UNI ? MAXW : 0;
+    VT pv = VT{T(0), T(0)};
+    int32_t pc = 0;
+    int pf_ns = 0;
+    int64_t pf_s0 = 0;
+    auto fetch_mat = [&](int64_t tile) {
+        const int64_t c0 = tile * CPT;
+        int64_t c1 = c0 + CPT;
+        if (c1 > a.n_chunks) c1 = a.n_chunks;
+        if (uw > 0) {
+            pf_s0 = c0 * 32 * uw;
+            pf_ns = static_cast<int>((c1 - c0) * 32 * uw);
+        } else {
+            pf_s0 = a.chunk_off[c0];
+            pf_ns = static_cast<int>(a.chunk_off[c1] - pf_s0);
+        }
+        if (tid < pf_ns) {
+            pv = gval[pf_s0 + tid];
+            pc = gcol[pf_s0 + tid];
+        }
+    };
+    auto deposit_mat = [&](int64_t tile, int b) {
+        if (tid < pf_ns) {
+            CHEBFD_WV(b)[tid] = pv;
+            CHEBFD_WC(b)[tid] = pc;
+        }
+        if (uw > 0) return;
+        if (tid < CPT) {
+            const int64_t c = tile * CPT + tid;
+            const bool in = c < a.n_chunks;
+            CHEBFD_WCOFF(b)[tid] = in ? static_cast<int32_t>(a.chunk_off[c] - pf_s0) : 0;
+            CHEBFD_WCW(b)[tid] = in ? a.chunk_width[c] : 0;
+        }
+    };
+    // one block of U rows: row blk * TR + rr, this lane's columns
+    auto ring_store = [&](int64_t blk, const PK &v) {
+        T *dst = reinterpret_cast<T *>(smem + ((blk * TR + rr) & (S::RING_ROWS - 1)) * RB + lane_off);
+        if constexpr (CPL == 2) {
+            *reinterpret_cast<float4 *>(dst) = float4{v.re[0], v.im[0], v.re[1], v.im[1]};
+        } else {
+            *reinterpret_cast<VT *>(dst) = VT{v.re[0], v.im[0]};
+        }
+    };
+    auto row_ok = [&](int64_t blk) { return blk >= 0 && blk < nblk && blk * TR + rr < a.n; };
+
+
+    // (the reduction above ends with a barrier: the ring area is free)
+    if (tb < te) {
+        // prologue: the window of the first tile and its matrix slots
+        PK pro[2 * kWinHalo + 1];
+#pragma unroll
+        for (int q = 0; q < 2 * kWinHalo + 1; ++q) {
+            const int64_t blk = tb - kWinHalo + q;
+            if (row_ok(blk)) pro[q] = load_pack<T, CPL, false>(P + 2 * ((blk * TR + rr) * NB + jc));
+        }
+        fetch_mat(tb);
+#pragma unroll
+        for (int q = 0; q < 2 * kWinHalo + 1; ++q) {
+            const int64_t blk = tb - kWinHalo + q;
+            if (row_ok(blk)) ring_store(blk, pro[q]);
+        }
+        deposit_mat(tb, 0);
+    }
+    __syncthreads();
+
+    int buf = 0;
+    for (int64_t tile = tb; tile < te; ++tile) {
+        const bool more = tile + 1 < te;
+        const int64_t t0 = tile * TR;
+        const int64_t i = t0 + rr;
+        const int wlo = static_cast<int>(t0) - kWinHalo * TR;   // window [wlo, wlo + (2 kWinHalo + 1) TR)
+        const VT *sv = CHEBFD_WV(buf);
+        const int32_t *sc = CHEBFD_WC(buf);
+
+        // slots of the row (entries past its width gather the row itself with
+        // coefficient 0; when every chunk holds MAXW slots per row the selects fold away)
+        // (UNI: every row has exactly MAXW slots, no selects)
+        int cc[MAXW];
+        int wdt = MAXW, base = 0;
+        if (i < a.n) {
+            const int cl = rr >> 5;
+            base = (UNI ? cl * 32 * MAXW : CHEBFD_WCOFF(buf)[cl]) + (rr & 31);
+            if constexpr (!UNI) wdt = CHEBFD_WCW(buf)[cl];
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) {
+                const bool act = UNI || k < wdt;
+                cc[k] = act ? sc[base + k * 32] : static_cast<int>(i);
+            }
+        }
+        // gathers outside the window go to global memory (issued before the
+        // prefetches, so waiting for them leaves the prefetches in flight)
+        PK u[MAXW];
+        bool inw[MAXW];
+        if (i < a.n) {
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) {
+                inw[k] = static_cast<unsigned>(cc[k] - wlo) < static_cast<unsigned>((2 * kWinHalo + 1) * TR);
+                if (!inw[k]) u[k] = load_pack<T, CPL, false>(P + 2 * ((int64_t)cc[k] * NB + jc));
+            }
+        }
+        // prefetches: next tile's matrix slots, W and Y rows; the block entering the window
+        PK rf;
+        const int64_t nb_in = tile + kWinHalo + 1;
+        const bool ring_in = more && row_ok(nb_in);
+        if (ring_in) rf = load_pack<T, CPL, false>(P + 2 * ((nb_in * TR + rr) * NB + jc));
+        if (more) fetch_mat(tile + 1);
+        // row streams of W and Y
+        PK o, yv;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) o.re[c] = o.im[c] = yv.re[c] = yv.im[c] = T(0);
+        if (i < a.n) {
+            const int64_t e = 2 * (i * NB + jc);
+            if constexpr (MODE != kModeFirst) o = load_pack<T, CPL, true>(static_cast<const T *>(a.O) + e);
+            if constexpr (MODE == kModeStep) yv = load_pack<T, CPL, true>(static_cast<const T *>(a.Y) + e);
+        }
+
+        if (i < a.n) {
+            const int64_t e = 2 * (i * NB + jc);
+            const PK up = load_pack<T, CPL, false>(CHEBFD_RING(i));
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k)
+                if (inw[k]) u[k] = load_pack<T, CPL, false>(CHEBFD_RING(cc[k]));
+
+            T acc_re[CPL], acc_im[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc_re[c] = acc_im[c] = T(0);
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) {
+                const bool act = UNI || k < wdt;
+                VT h = sv[act ? base + k * 32 : 0];
+                if (!act) h = VT{T(0), T(0)};
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    acc_re[c] = fma(h.x, u[k].re[c], acc_re[c]);
+                    acc_re[c] = fma(-h.y, u[k].im[c], acc_re[c]);
+                    acc_im[c] = fma(h.x, u[k].im[c], acc_im[c]);
+                    acc_im[c] = fma(h.y, u[k].re[c], acc_im[c]);
+                }
+            }
+            PK nw;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const T hu_re = fma(alpha, acc_re[c], beta * up.re[c]);
+                const T hu_im = fma(alpha, acc_im[c], beta * up.im[c]);
+                if constexpr (MODE == kModeFirst) {
+                    nw.re[c] = hu_re;
+                    nw.im[c] = hu_im;
+                } else {
+                    nw.re[c] = fma(T(2), hu_re, -o.re[c]);
+                    nw.im[c] = fma(T(2), hu_im, -o.im[c]);
+                }
+            }
+            if constexpr (MODE == kModeFirst) {
+                store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
+            } else if constexpr (MODE == kModeSecond) {
+                store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
+                PK y;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    y.re[c] = fma(g0, o.re[c], fma(g1, up.re[c], g2 * nw.re[c]));
+                    y.im[c] = fma(g0, o.im[c], fma(g1, up.im[c], g2 * nw.im[c]));
+                }
+                store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, y);  // Y aliases O: row i's entry is read only here
+            } else {
+                store_pack_nt<T, CPL>(static_cast<T *>(a.O) + e, nw);
+                if constexpr (MODE == kModeStep) {
+                    PK y;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        y.re[c] = fma(g2, nw.re[c], yv.re[c]);
+                        y.im[c] = fma(g2, nw.im[c], yv.im[c]);
+                    }
+                    store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, y);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const double nr = nw.re[c], ni = nw.im[c], ur = up.re[c], ui = up.im[c];
+                e_re[c] = fma(nr, ur, fma(ni, ui, e_re[c]));
+                e_im[c] = fma(nr, ui, fma(-ni, ur, e_im[c]));
+                nu[c] = fma(ur, ur, fma(ui, ui, nu[c]));
+            }
+        }
+        // block tile + kWinHalo + 1 replaces block tile - kWinHalo - 1 (outside
+        // this tile's window); the next tile's slots go to the idle buffer
+        if (ring_in) ring_store(nb_in, rf);
+        if (more) deposit_mat(tile + 1, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    // workgroup reduction over the TR lanes of each column, fixed order;
+    // sred[(component * CPL + c) * kWinThreads + lane] (over the ring: every
+    // wave has passed the last barrier of the tile loop)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        sred[(0 * CPL + c) * kWinThreads + tid] = e_re[c];
+        sred[(1 * CPL + c) * kWinThreads + tid] = e_im[c];
+        sred[(2 * CPL + c) * kWinThreads + tid] = nu[c];
+    }
+    __syncthreads();
+    if (tid < NB) {
+        const int lj = tid / CPL, c = tid % CPL;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int q = 0; q < TR; ++q) {
+            s0 += sred[(0 * CPL + c) * kWinThreads + q * LPR + lj];
+            s1 += sred[(1 * CPL + c) * kWinThreads + q * LPR + lj];
+            s2 += sred[(2 * CPL + c) * kWinThreads + q * LPR + lj];
+        }
+        a.part_out[(int64_t)(0 * NB + tid) * G + w] = s0;
+        a.part_out[(int64_t)(1 * NB + tid) * G + w] = s1;
+        a.part_out[(int64_t)(2 * NB + tid) * G + w] = s2;
+    }
+}
+#undef CHEBFD_WV
+#undef CHEBFD_WC
+#undef CHEBFD_WCOFF
+#undef CHEBFD_WCW
+#undef CHEBFD_RING
+
+namespace {
+
+template <typename T, int NB, int MODE, int MAXW, bool UNI>
+int launch_win_one(const StepArgs &a, const WinGeometry &g, hipStream_t s) {
+    constexpr int lds = win_lds_bytes<T, NB, MAXW>();
+    hipLaunchKernelGGL((cheb_win_kernel<T, NB, MODE, MAXW, UNI>), dim3(g.G), dim3(kWinThreads), lds, s, a,
+                       g.ntiles);
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+template <typename T, int NB, int MAXW, bool UNI>
+int launch_win_mode(int mode, const StepArgs &a, const WinGeometry &g, hipStream_t s) {
+    switch (mode) {
+        case kModeFirst: return launch_win_one<T, NB, kModeFirst, MAXW, UNI>(a, g, s);
+        case kModeSecond: return launch_win_one<T, NB, kModeSecond, MAXW, UNI>(a, g, s);
+        case kModeStep: return launch_win_one<T, NB, kModeStep, MAXW, UNI>(a, g, s);
+        case kModeKpm: return launch_win_one<T, NB, kModeKpm, MAXW, UNI>(a, g, s);
+    }
+    CHEBFD_FAIL(CHEBFD_EINVAL, "bad step mode %d", mode);
+}
+
+template <typename T, int NB>
+int launch_win_w(int mode, const StepArgs &a, const WinGeometry &g, hipStream_t s) {
+    if (g.uniform) return launch_win_mode<T, NB, kWinWidth, true>(mode, a, g, s);
+    return launch_win_mode<T, NB, kWinWidth, false>(mode, a, g, s);
+}
+
+template <typename T, int NB, int MAXW, bool UNI>
+bool set_win_attr() {
+    const int bytes = win_lds_bytes<T, NB, MAXW>();
+    bool ok = true;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void *>(cheb_win_kernel<T, NB, kModeFirst, MAXW, UNI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void *>(cheb_win_kernel<T, NB, kModeSecond, MAXW, UNI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void *>(cheb_win_kernel<T, NB, kModeStep, MAXW, UNI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void *>(cheb_win_kernel<T, NB, kModeKpm, MAXW, UNI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    return ok;
+}
+
+}  // namespace
+
+bool win_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, WinGeometry *g) {
+    if (H->C != 32 || H->max_width > kWinWidth) return false;
+    int tr;
+    // instances where the window beats the LDS-staged kernel (measured); c64 with
+    // n_b = 32 is not among them: its step already runs near the stream rate
+    if (prec == CHEBFD_PREC_FP64 && nb == 32)
+        tr = WinShape<double, 32>::TR;
+    else if (prec == CHEBFD_PREC_MIXED && nb == 64)
+        tr = WinShape<float, 64>::TR;
+    else
+        return false;
+    const int local = H->window_local[tr == 32 ? 0 : 1];
+    if (local < kWinMinLocal) return false;
+    g->tr = tr;
+    // every chunk exactly kWinWidth slots wide (lattice Hamiltonians of 4 orbitals): no width selects
+    g->uniform = H->uniform_width == kWinWidth ? 1 : 0;
+    g->ntiles = (H->n + tr - 1) / tr;
+    // one workgroup per CU, at least two tiles each (the window needs a sweep to pay off)
+    int64_t G = num_cus;
+    while (G > kXcdCount && g->ntiles < 2 * G) G /= 2;
+    if (g->ntiles < 2 * G) return false;
+    static bool attr_ok =
+        set_win_attr<double, 32, kWinWidth, true>() && set_win_attr<double, 32, kWinWidth, false>() &&
+        set_win_attr<float, 64, kWinWidth, true>() && set_win_attr<float, 64, kWinWidth, false>();
+    if (!attr_ok) return false;
+    g->G = static_cast<int>(G);
+    return true;
+}
+
+int launch_win_step(int prec, int nb, int mode, const StepArgs &a, const WinGeometry &g, hipStream_t s) {
+    if (prec == CHEBFD_PREC_FP64 && nb == 32) return launch_win_w<double, 32>(mode, a, g, s);
+    if (prec == CHEBFD_PREC_MIXED && nb == 64) return launch_win_w<float, 64>(mode, a, g, s);
+    CHEBFD_FAIL(CHEBFD_EINVAL, "window kernel has no instance for prec %d, n_b = %d", prec, nb);
+}
+
+}  // namespace chebfd

@@ -53,6 +53,24 @@ struct LdsGeometry {
 bool lds_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, LdsGeometry *g);
 int launch_lds_step(int prec, int nb, int mode, const StepArgs &a, const LdsGeometry &g,
                     hipStream_t s);
+// Window step kernel (filter_win.hip): one 1024-thread workgroup per CU sweeps
+// a contiguous range of tiles and gathers from a ring of U rows staged in LDS
+// (kWinBlocks blocks of one tile each; tile t reads blocks t - kWinHalo ..
+// t + kWinHalo).  Used for FP64 n_b = 32 and c64 n_b = 64, rows of at most
+// kWinWidth entries, when at least kWinMinLocal of 1000 stored entries fall
+// inside the window.
+constexpr int kWinBlocks = 8;
+constexpr int kWinHalo = 3;
+constexpr int kWinWidth = 13;       // rows of at most this many stored entries
+constexpr int kWinMinLocal = 700;
+struct WinGeometry {
+    int tr;             // rows per tile
+    int uniform;        // 1: every chunk holds exactly kWinWidth slots per row
+    int G;              // workgroups (one per CU)
+    int64_t ntiles;
+};
+bool win_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, WinGeometry *g);
+int launch_win_step(int prec, int nb, int mode, const StepArgs &a, const WinGeometry &g, hipStream_t s);
 // row-per-wavefront kernel for n_b in {32, 64, 128}: a pass covers 128 / n_b rows
 // Rows up to kRowMaxUnrolled stored entries use the unrolled path, whose loads
 // may read up to kRowMaxUnrolled * C slots past the last chunk: the matrix

@@ -38,13 +38,15 @@ def test_neighbour_distances_shrink():
 
 def test_pencil_order_keeps_z_neighbours_close():
     Nx, Ny, Nz = 128, 128, 64
-    o = lattice_row_order(Nx, Ny, Nz)                      # 8 x 4 pencils
-    pos = np.empty(o.size, dtype=np.int64)
-    pos[o] = np.arange(o.size)
     s = np.arange(Nx * Ny * Nz)
     x, y, z = s % Nx, (s // Nx) % Ny, s // (Nx * Ny)
     zn = x + Nx * (y + Ny * ((z + 1) % Nz))
-    d = np.abs(pos[4 * zn] - pos[4 * s])
-    assert np.median(d) == 4 * 8 * 4
+    for pencil in ((4, 4), (8, 4)):                        # default 4 x 4
+        o = lattice_row_order(Nx, Ny, Nz, pencil=pencil)
+        pos = np.empty(o.size, dtype=np.int64)
+        pos[o] = np.arange(o.size)
+        d = np.abs(pos[4 * zn] - pos[4 * s])
+        assert np.median(d) == 4 * pencil[0] * pencil[1]
+    assert np.array_equal(lattice_row_order(Nx, Ny, Nz), lattice_row_order(Nx, Ny, Nz, pencil=(4, 4)))
     o2 = lattice_row_order(6, 5, 4)                        # pencils do not divide: slabs
     assert np.array_equal(np.sort(o2), np.arange(o2.size))
