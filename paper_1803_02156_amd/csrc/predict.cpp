@@ -80,16 +80,18 @@ int chebfd_choose_params(double a, double b, double count_est, int32_t n_b, cons
                    n_b);
     CHEBFD_REQUIRE(pr != nullptr, "predictor is NULL");
     const double nhat = std::max(count_est, 0.0);
+    const double delta = (b - a) / 2.0;
     double np_real, ns_real;
     if (h_mlp_out) {
+        // the network's outputs: standardised log(n_p delta) and log(n_s / max(n_hat, 1))
         CHEBFD_REQUIRE(std::isfinite(h_mlp_out[0]) && std::isfinite(h_mlp_out[1]), "MLP output not finite");
         CHEBFD_REQUIRE(pr->t_std[0] > 0.0 && pr->t_std[1] > 0.0, "predictor scales must be positive");
-        np_real = std::exp(std::min(30.0, h_mlp_out[0] * pr->t_std[0] + pr->t_mean[0]));
-        ns_real = std::exp(std::min(30.0, h_mlp_out[1] * pr->t_std[1] + pr->t_mean[1]));
+        np_real = std::exp(std::min(30.0, h_mlp_out[0] * pr->t_std[0] + pr->t_mean[0])) / delta;
+        ns_real = std::exp(std::min(30.0, h_mlp_out[1] * pr->t_std[1] + pr->t_mean[1])) * std::max(nhat, 1.0);
         ns_real = std::max(ns_real, 1.2 * nhat);
     } else {
         CHEBFD_REQUIRE(pr->kappa > 0.0, "kappa must be positive");
-        np_real = std::round(pr->kappa / ((b - a) / 2.0));
+        np_real = pr->kappa / delta;
         ns_real = 2.0 * nhat;
     }
     const double np_c = std::min<double>(CHEBFD_NP_MAX, std::max<double>(CHEBFD_NP_MIN, std::round(np_real)));

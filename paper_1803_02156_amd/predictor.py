@@ -17,8 +17,12 @@ solved (or, adaptively, n_p is doubled from the heuristic's until the solver
 finds pairs, then one more doubling and one wider subspace are tried), and the
 label is the run with the least deterministic work
 ``iters (n_p n_s nnz + c_orth n n_s^2)`` among the runs that converged with the
-full eigenvalue count; the network regresses the standardised
-(log n_p, log n_s) of that point.
+full eigenvalue count; the network regresses the standardised logs of the
+two scale-free ratios of that point, n_p delta~ (delta~ the half width of the
+scaled interval) and n_s / max(n_hat, 1) (n_hat the count estimate): the
+interval and the count estimate already carry the matrix size, so the ratios
+learnt on small lattices transfer to large ones.  The heuristic's kappa is the
+median n_p delta~ of the training labels.
 
 Every computation runs in libchebfd; this file only orchestrates runs and
 stores their results (numpy on the host).
@@ -175,6 +179,21 @@ def features_of(row: dict) -> np.ndarray:
     return f
 
 
+def targets(rows: list) -> np.ndarray:
+    """The regression targets of labelled corpus rows: (n_p delta~, n_s / max(n_hat, 1))."""
+    out = []
+    for r in rows:
+        a, b = float(r["features"][256]), float(r["features"][257])
+        n_p, n_s = r["label"]
+        out.append((n_p * (b - a) / 2.0, n_s / max(float(r["count_est"]), 1.0)))
+    return np.array(out, dtype=np.float64)
+
+
+def kappa_from_corpus(rows: list) -> float:
+    """The heuristic's constant: the median n_p delta~ of the labels."""
+    return float(np.median(targets(rows)[:, 0]))
+
+
 def standardise(labels: np.ndarray):
     lg = np.log(labels.astype(np.float64))
     mean = lg.mean(axis=0)
@@ -313,7 +332,8 @@ def main(argv=None):
     k.add_argument("--dims", type=int, nargs=3, default=(16, 16, 8))
     t = sub.add_parser("train")
     t.add_argument("--corpus", nargs="+", required=True)
-    t.add_argument("--kappa", type=float, required=True)
+    t.add_argument("--kappa", type=float, default=None,
+                   help="heuristic constant stored with the weights (default: median n_p delta~ of the labels)")
     t.add_argument("--steps", type=int, default=3000)
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
     e = sub.add_parser("eval")
@@ -334,10 +354,13 @@ def main(argv=None):
     elif a.cmd == "train":
         rows = [r for p in a.corpus for r in json.load(open(p)) if r["label"] is not None and r["full_count"] > 0]
         X = np.array([features_of(r) for r in rows], dtype=np.float32)
-        T, mean, std = standardise(np.array([r["label"] for r in rows], dtype=np.float64))
+        T, mean, std = standardise(targets(rows))
+        kappa = kappa_from_corpus(rows) if a.kappa is None else a.kappa
         params = train(X, T, steps=a.steps, log=log)
-        save(a.out, params, mean, std, a.kappa, {"train_instances": len(rows), "steps": a.steps,
-                                                  "corpus": [os.path.basename(p) for p in a.corpus]})
+        save(a.out, params, mean, std, kappa, {"train_instances": len(rows), "steps": a.steps,
+                                               "targets": "log(n_p delta), log(n_s / max(n_hat, 1))",
+                                               "corpus": [os.path.basename(p) for p in a.corpus]})
+        log(f"# kappa {kappa:.3f}")
         log(f"# saved {a.out}")
     elif a.cmd == "eval":
         rows = [r for p in a.corpus for r in json.load(open(p))]

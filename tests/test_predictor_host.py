@@ -40,3 +40,25 @@ def test_work_units_and_summary():
     assert s["heuristic"]["failures"] == 1 and s["mlp"]["failures"] == 0
     assert s["work_ratio_mlp_over_heuristic"]["mean"] == 0.5
     assert s["mlp"]["mean_iters"] == 2.5
+
+
+def test_targets_invert_through_choose_params():
+    """A label, turned into the network's targets and standardised, comes back
+    out of the parameter rule (oracle reading) as the same (n_p, n_s)."""
+    import oracle as O
+    rows = []
+    for n_p, n_s, a, b, cnt in ((800, 96, -0.02, 0.03, 37.0), (1600, 64, -0.011, 0.009, 20.5),
+                                (400, 128, -0.05, 0.05, 0.4)):
+        f = np.zeros(258, dtype=np.float32)
+        f[256], f[257] = a, b
+        rows.append(dict(features=f.tolist(), label=(n_p, n_s), count_est=cnt))
+    T = PR.targets(rows)
+    f32 = lambda v: float(np.float32(v))  # noqa: E731  features are stored as FP32
+    assert np.allclose(T[:, 0], [800 * (f32(0.03) - f32(-0.02)) / 2, 1600 * (f32(0.009) - f32(-0.011)) / 2,
+                                 400 * (f32(0.05) - f32(-0.05)) / 2])
+    assert np.allclose(T[:, 1], [96 / 37.0, 64 / 20.5, 128 / 1.0])
+    z, mean, std = PR.standardise(T)
+    for r, zz in zip(rows, z):
+        a, b = r["features"][256], r["features"][257]
+        assert O.choose_params(a, b, r["count_est"], 32, mlp_out=zz, t_mean=mean, t_std=std) == tuple(r["label"])
+    assert PR.kappa_from_corpus(rows) == np.median(T[:, 0])
