@@ -44,7 +44,7 @@ def _split(dims, parts):
 
 
 def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int = 8, slab: int = 8,
-                      pencil=(4, 4)):
+                      pencil=(4, 4), sweeps: int = 32):
     """Row order (int32 permutation of 0..n-1, order[k] = original row placed k-th) for a
     lattice with site index x + Nx (y + Ny z) and row orbitals * site + orbital.
 
@@ -53,7 +53,15 @@ def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int =
     the same or an adjacent pencil; with ``pencil=None``, or when px, py do not
     divide the box extents, y-slabs of ``slab`` lines are swept z-plane by z-plane
     instead.  Falls back to fewer boxes when the extents do not split evenly, and
-    to slabs of the full box width when ``slab`` does not divide it."""
+    to slabs of the full box width when ``slab`` does not divide it.
+
+    ``sweeps``: the window step kernel splits each box's rows into this many
+    contiguous ranges, swept side by side by the workgroups of one XCD (32 CUs
+    per XCD).  When it divides the number of pencils of a box, pencil p is put
+    into range p % sweeps (at position p // sweeps), so the pencils next to p in
+    x and y are swept at the same time by other workgroups of the same XCD and
+    the gathers that leave a workgroup's LDS window find their rows in L2.
+    ``sweeps=1`` keeps the pencils in x-fastest order."""
     dims = (int(Nx), int(Ny), int(Nz))
     split = None
     while parts >= 1 and split is None:
@@ -73,7 +81,11 @@ def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int =
         # pencils of px x py sites swept along z: z-neighbours px py sites apart
         px, py = pencil
         lx = x % bx
-        key = np.lexsort((lx % px, ly % py, z % bz, lx // px, ly // py, box))
+        npx, npen = bx // px, (bx // px) * (by // py)
+        pen = lx // px + npx * (ly // py)                   # pencil index in the box, x fastest
+        if sweeps > 1 and npen % sweeps == 0:
+            pen = (pen % sweeps) * (npen // sweeps) + pen // sweeps
+        key = np.lexsort((lx % px, ly % py, z % bz, pen, box))
     else:
         key = np.lexsort((x % bx, ly, z % bz, ly // sy, box))
     sites = site[key]

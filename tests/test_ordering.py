@@ -50,3 +50,28 @@ def test_pencil_order_keeps_z_neighbours_close():
     assert np.array_equal(lattice_row_order(Nx, Ny, Nz), lattice_row_order(Nx, Ny, Nz, pencil=(4, 4)))
     o2 = lattice_row_order(6, 5, 4)                        # pencils do not divide: slabs
     assert np.array_equal(np.sort(o2), np.arange(o2.size))
+
+
+def test_pencils_interleaved_over_sweeps():
+    """With sweeps = 32, a site's x- or y-neighbour in another pencil of the same
+    box sits in another sweep range at nearly the same offset: the ranges, swept
+    side by side, reach both rows at about the same time.  (128x128x64: boxes of
+    32 x 64 x 64 sites, 128 pencils of 4096 rows per box, 4 per range.)"""
+    Nx, Ny, Nz = 128, 128, 64
+    n_rows = 4 * Nx * Ny * Nz
+    box_rows, span = n_rows // 8, n_rows // (8 * 32)
+    s = np.arange(Nx * Ny * Nz)
+    x, y, z = s % Nx, (s // Nx) % Ny, s // (Nx * Ny)
+    nbrs = ((x + 1) % Nx + Nx * (y + Ny * z), x + Nx * ((y + 1) % Ny + Ny * z))
+    # sweeps = 32, y: pencil rows r -> r + 1 with r % 4 == 3 (3 of the 15 inside a box) wrap to the
+    # next position.  sweeps = 1 (x-fastest pencils, 4 to a range): x-neighbour pencils share a
+    # range, 4084 rows apart; y-neighbour pencils (8 on) happen to sit two ranges on, aligned.
+    for sweeps, bounds in ((32, ((1.0, 1.0), (0.79, 0.81))), (1, ((0.0, 0.0), (1.0, 1.0)))):
+        o = lattice_row_order(Nx, Ny, Nz, sweeps=sweeps)
+        pos = np.empty(o.size, dtype=np.int64)
+        pos[o] = np.arange(o.size)
+        for nb, (lo, hi) in zip(nbrs, bounds):
+            a, b = pos[4 * s], pos[4 * nb]
+            far = (a // box_rows == b // box_rows) & (np.abs(a - b) > 96)   # same box, outside the window
+            close = np.mean(np.abs(a[far] % span - b[far] % span) <= 64)
+            assert lo <= close <= hi, (sweeps, close)
