@@ -326,10 +326,10 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
  *    n_p = clamp(round(kappa / delta), 50, 20000) with delta = (b~ - a~) / 2
  *    the half width of the scaled interval and n_hat the eigenvalue count
  *    estimate from the moments;
- *  - a small MLP (below) on the moment features, whose two outputs are the
- *    two scale-free ratios of that rule, standardised: log(n_p delta) (its
- *    own kappa) and log(n_s / max(n_hat, 1)).  Ratios transfer across
- *    matrix sizes: delta and n_hat already carry the size.
+ *  - a small MLP (below) on the moment features, whose two outputs are
+ *    scale-free ratios, standardised: log(n_p delta) (its own kappa) and
+ *    log(n_s / max(2 n_hat, n_b)) (its factor on the heuristic's n_s).  Ratios
+ *    transfer across matrix sizes: delta and n_hat already carry the size.
  */
 #define CHEBFD_FEATURE_R        16   /* random-phase vectors of the feature moments */
 #define CHEBFD_FEATURE_MOMENTS  256  /* moments mu~_0 .. mu~_255 (128 Chebyshev steps) */
@@ -342,7 +342,7 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
 
 typedef struct chebfd_predictor {
     double kappa;           /* heuristic: n_p = kappa / delta */
-    double t_mean[2];       /* MLP output de-standardisation: log(n_p delta), log(n_s / max(n_hat, 1)) */
+    double t_mean[2];       /* MLP output de-standardisation: log(n_p delta), log(n_s / max(2 n_hat, n_b)) */
     double t_std[2];
 } chebfd_predictor;
 
@@ -365,8 +365,8 @@ int chebfd_features(const chebfd_matrix *H, double lam_L, double lam_R, uint64_t
 /*
  * (n_p, n_s) from the scaled interval [a, b], the count estimate and either the
  * MLP's two outputs (h_mlp_out, host: standardised log(n_p delta) and
- * log(n_s / max(n_hat, 1)), so n_p = exp(t_std[0] y0 + t_mean[0]) / delta and
- * n_s = exp(t_std[1] y1 + t_mean[1]) max(n_hat, 1)) or, with h_mlp_out NULL,
+ * log(n_s / max(2 n_hat, n_b)), so n_p = exp(t_std[0] y0 + t_mean[0]) / delta
+ * and n_s = exp(t_std[1] y1 + t_mean[1]) max(2 n_hat, n_b)) or, with h_mlp_out NULL,
  * the heuristic.  Both are clamped: n_p to
  * [CHEBFD_NP_MIN, CHEBFD_NP_MAX]; n_s to a multiple of n_b that is at least
  * max(n_b, 1.2 n_hat) and at most 512.  Host only, no device work.

@@ -214,9 +214,10 @@ def choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, 
     and n_p around 10^3 for its problems (Sect. 5); it gives no rule.  The
     reading used here: the filter's resolution scales like 1 / n_p in the
     scaled variable, so n_p = kappa / delta with delta = (b - a) / 2, and
-    n_s = 2 n_hat rounded up to a block.  A network may instead give the two
-    scale-free ratios of that rule, standardised: log(n_p delta) (its own kappa)
-    and log(n_s / max(n_hat, 1)); n_s then stays at least 1.2 n_hat.
+    n_s = 2 n_hat rounded up to a block.  A network may instead give two
+    scale-free ratios, standardised: log(n_p delta) (its own kappa) and
+    log(n_s / max(2 n_hat, n_b)) (its factor on the heuristic's n_s); n_s then
+    stays at least 1.2 n_hat.
     Clamped: n_p in [np_min, np_max], n_s a multiple of n_b in [n_b, ns_max].
     """
     nhat = max(count_est, 0.0)
@@ -226,7 +227,7 @@ def choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, 
         ns_real = 2.0 * nhat
     else:
         np_real = math.exp(min(30.0, float(mlp_out[0]) * t_std[0] + t_mean[0])) / delta
-        ns_real = max(math.exp(min(30.0, float(mlp_out[1]) * t_std[1] + t_mean[1])) * max(nhat, 1.0),
+        ns_real = max(math.exp(min(30.0, float(mlp_out[1]) * t_std[1] + t_mean[1])) * max(2.0 * nhat, n_b),
                       1.2 * nhat)
     n_p = int(min(np_max, max(np_min, math.floor(np_real + 0.5))))   # halves round up
     n_s = int(math.ceil(ns_real / n_b) * n_b)

@@ -17,11 +17,12 @@ solved (or, adaptively, n_p is doubled from the heuristic's until the solver
 finds pairs, then one more doubling and one wider subspace are tried), and the
 label is the run with the least deterministic work
 ``iters (n_p n_s nnz + c_orth n n_s^2)`` among the runs that converged with the
-full eigenvalue count; the network regresses the standardised logs of the
-two scale-free ratios of that point, n_p delta~ (delta~ the half width of the
-scaled interval) and n_s / max(n_hat, 1) (n_hat the count estimate): the
-interval and the count estimate already carry the matrix size, so the ratios
-learnt on small lattices transfer to large ones.  The heuristic's kappa is the
+full eigenvalue count; the network regresses the standardised logs of two
+scale-free ratios of that point, n_p delta~ (delta~ the half width of the
+scaled interval) and n_s / max(2 n_hat, n_b) (n_hat the count estimate; the
+heuristic's own n_s before rounding): the interval and the count estimate
+already carry the matrix size, so the ratios learnt on small lattices transfer
+to large ones.  The heuristic's kappa is the
 median n_p delta~ of the training labels.
 
 Every computation runs in libchebfd; this file only orchestrates runs and
@@ -180,12 +181,12 @@ def features_of(row: dict) -> np.ndarray:
 
 
 def targets(rows: list) -> np.ndarray:
-    """The regression targets of labelled corpus rows: (n_p delta~, n_s / max(n_hat, 1))."""
+    """The regression targets of labelled corpus rows: (n_p delta~, n_s / max(2 n_hat, n_b))."""
     out = []
     for r in rows:
         a, b = float(r["features"][256]), float(r["features"][257])
         n_p, n_s = r["label"]
-        out.append((n_p * (b - a) / 2.0, n_s / max(float(r["count_est"]), 1.0)))
+        out.append((n_p * (b - a) / 2.0, n_s / max(2.0 * float(r["count_est"]), float(N_B))))
     return np.array(out, dtype=np.float64)
 
 
@@ -358,7 +359,7 @@ def main(argv=None):
         kappa = kappa_from_corpus(rows) if a.kappa is None else a.kappa
         params = train(X, T, steps=a.steps, log=log)
         save(a.out, params, mean, std, kappa, {"train_instances": len(rows), "steps": a.steps,
-                                               "targets": "log(n_p delta), log(n_s / max(n_hat, 1))",
+                                               "targets": "log(n_p delta), log(n_s / max(2 n_hat, n_b))",
                                                "corpus": [os.path.basename(p) for p in a.corpus]})
         log(f"# kappa {kappa:.3f}")
         log(f"# saved {a.out}")

@@ -307,12 +307,12 @@ def test_choose_params_reading():
     assert O.choose_params(-0.01, 0.01, 47.3, 32, kappa=2.0) == (200, 96)
     assert O.choose_params(-0.5, 0.5, 0.0, 16, kappa=2.0) == (50, 16)           # both floors
     assert O.choose_params(-1e-5, 1e-5, 1e4, 32, kappa=2.0) == (20000, 512)     # both ceilings
-    # network outputs are de-standardised logs of n_p delta and n_s / n_hat;
+    # network outputs are de-standardised logs of n_p delta and n_s / max(2 n_hat, n_b);
     # n_s kept >= 1.2 n_hat
-    n_p, n_s = O.choose_params(-0.1, 0.1, 100.0, 32, mlp_out=(0.0, 0.0), t_mean=(np.log(80.0), np.log(0.4)))
-    assert n_p == 800 and n_s == 128
-    n_p, n_s = O.choose_params(-0.02, 0.06, 100.0, 32, mlp_out=(1.0, -1.0), t_mean=(np.log(10.0), np.log(6.0)),
+    n_p, n_s = O.choose_params(-0.1, 0.1, 100.0, 32, mlp_out=(0.0, 0.0), t_mean=(np.log(80.0), np.log(0.2)))
+    assert n_p == 800 and n_s == 128                                            # 1.2 n_hat = 120 -> 128
+    n_p, n_s = O.choose_params(-0.02, 0.06, 100.0, 32, mlp_out=(1.0, -1.0), t_mean=(np.log(10.0), np.log(3.0)),
                                t_std=(np.log(2.0), np.log(2.0)))
-    assert n_p == 500 and n_s == 320                                            # 20 / 0.04, 3 x 100
-    n_p, n_s = O.choose_params(-0.1, 0.1, 0.3, 32, mlp_out=(0.0, 0.0), t_mean=(np.log(20.0), np.log(40.0)))
-    assert n_p == 200 and n_s == 64                                             # n_hat < 1 counts as 1
+    assert n_p == 500 and n_s == 320                                            # 20 / 0.04, 1.5 x 200
+    n_p, n_s = O.choose_params(-0.1, 0.1, 3.0, 32, mlp_out=(0.0, 0.0), t_mean=(np.log(20.0), np.log(1.5)))
+    assert n_p == 200 and n_s == 64                                             # 2 n_hat < n_b: 1.5 x 32

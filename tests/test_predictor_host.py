@@ -56,7 +56,7 @@ def test_targets_invert_through_choose_params():
     f32 = lambda v: float(np.float32(v))  # noqa: E731  features are stored as FP32
     assert np.allclose(T[:, 0], [800 * (f32(0.03) - f32(-0.02)) / 2, 1600 * (f32(0.009) - f32(-0.011)) / 2,
                                  400 * (f32(0.05) - f32(-0.05)) / 2])
-    assert np.allclose(T[:, 1], [96 / 37.0, 64 / 20.5, 128 / 1.0])
+    assert np.allclose(T[:, 1], [96 / 74.0, 64 / 41.0, 128 / 32.0])
     z, mean, std = PR.standardise(T)
     for r, zz in zip(rows, z):
         a, b = r["features"][256], r["features"][257]
