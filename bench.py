@@ -9,10 +9,11 @@ Inputs are synthetic and resident in HBM before the timed region.
 
 Prints one JSON line: the filter's algorithmic HBM bandwidth (the paper's
 minimum-traffic model, Sect. 3.4) as `value`, the roofline of the fused step
-kernel (its launches timed on their own), the time to converged Ritz pairs of
-the whole iteration in FP64 and in mixed precision on the same matrix, and the
-FP64 CPU oracle timed on a bounded sample of the same workload on the host
-cores.
+kernel (its launches timed on their own), the same filter with c64 block
+vectors (`filter_mixed`), the time to converged Ritz pairs of the whole
+iteration in FP64, in mixed precision and in mixed precision with the learned
+(n_p, n_s) on the same matrix, and the FP64 CPU oracle timed on a bounded
+sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -46,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample (0 disables)")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-converged leg")
+    ap.add_argument("--no-mixed-filter", action="store_true",
+                    help="skip the c64 filter leg (timed after the FP64 filter when --prec 0)")
     ap.add_argument("--solve-prec", choices=("both", "fp64", "mixed"), default="both",
                     help="precisions of the time-to-converged leg")
     ap.add_argument("--solve-count", type=float, default=100.0,
@@ -83,6 +86,55 @@ def counter_traffic(kind: int, prec: int, n_b: int, lattice: str, order: str):
     if t.get("kernel_source_sha256_16") != kernel_source_hash(kind):
         return None
     return t["hbm_bytes_per_launch"]
+
+
+def mixed_filter_leg(P, H, order, lattice, order_name, n_s, n_b, n_p, steps):
+    """The same full filter with c64 block vectors and a c64 matrix (the mixed
+    precision's filter stage): algorithmic GB/s, the fused step's average launch
+    and the step kernel with its committed HBM traffic."""
+    import torch
+    from paper_1803_02156_amd import traffic
+    from topi import random_phase_block
+    n, nnz = len(H[0]) - 1, len(H[1])
+    M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=1, order=order)
+    lo, hi = P.chebfd_bounds(M)
+    al, be, gam = P.chebfd_coefficients(lo, hi, -0.1, 0.1, n_p)
+    X0 = random_phase_block(n, n_s, 45)
+    x0 = torch.empty((n_s, n), dtype=torch.complex128, device="cuda")
+    x0.copy_(torch.from_numpy(np.ascontiguousarray(X0.T)))
+    del X0
+    xb0 = P.chebfd_pack(M, x0.T, n_b)
+    del x0
+    xy = torch.empty_like(xb0)
+    work = P.FilterWork(M, n_b, n_p, n_s, moments=True)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        xy.copy_(xb0)
+        P.chebfd_filter(M, al, be, gam, n_s, n_b, xy, work=work)
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = traffic.filter_bytes(n, nnz, n_s, n_b, n_p, 1) / (ms * 1e-3) / 1e9
+    avg_launch_s = ms * 1e-3 / ((n_s // n_b) * n_p)
+    r, w = traffic.step_bytes(n, nnz, n_b, 1)
+    kind = P.chebfd_step_kernel(M, n_b)
+    out = {"value": round(gbs, 2), "unit": "GB/s", "ms_per_filter": round(ms, 3),
+           "pct_of_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+           "kernel": f"{STEP_KERNELS[kind][0]}_kernel<float,{n_b},kModeStep>",
+           "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": r + w,
+           "frac": round((r + w) / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4),
+           "traffic": counter_traffic(kind, 1, n_b, lattice, order_name),
+           "kernel_source_sha256_16": kernel_source_hash(kind)}
+    del xy, xb0, work, M
+    torch.cuda.empty_cache()
+    return out
 
 
 def interval_for_count(P, M, target, seed=7, n_steps=1024, R=16):
@@ -320,6 +372,12 @@ def main():
     copy_gbs = 10 * 2 * 8 * cnt / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del pa, pb
 
+    mixed = None
+    if prec == 0 and not args.no_mixed_filter:
+        mixed = mixed_filter_leg(P, H, order, args.lattice, args.order, n_s, n_b, n_p, args.steps)
+        print(f"# mixed filter: {mixed['value']:.0f} GB/s, {mixed['avg_launch_us']:.1f} us per step",
+              file=sys.stderr, flush=True)
+
     solve = None
     if not args.no_solve:
         del xy, xb0, work
@@ -369,6 +427,7 @@ def main():
         "gram": {"kernel": "gram_kernel (FP64 MFMA 16x16x4)", "shape": f"{n} x {n_s} x {n_s} complex",
                  "ms": round(gram_ms, 3), "tflops": round(gram_tflops, 2),
                  "frac_of_fp64_mfma_peak": round(gram_tflops / 78.6, 4)},
+        "filter_mixed": mixed,
         "time_to_converged": solve,
         "cpu_baseline": cpu,
     }
