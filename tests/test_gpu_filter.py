@@ -239,3 +239,55 @@ def test_filter_parity_with_row_order(P, prec, which):
     bnd = _bound(n_p, 13, u, s) * np.sum(np.abs(gam))
     assert np.max(np.abs(Y - Yr)) <= bnd
     assert np.max(np.abs(nu.cpu().numpy()[1:] - nur[1:])) <= n * _bound(n_p, 13, u, s) * 4
+
+
+def _csr_from_entries(n, entries):
+    """CRS arrays of a Hermitian matrix from (i, j, value) with i <= j (mirrored)."""
+    rows = [[] for _ in range(n)]
+    for i, j, v in entries:
+        rows[i].append((j, v))
+        if i != j:
+            rows[j].append((i, np.conj(v)))
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col, val = [], []
+    for i in range(n):
+        for j, v in sorted(rows[i]):
+            col.append(j)
+            val.append(v)
+        rowptr[i + 1] = len(col)
+    return rowptr, np.array(col, dtype=np.int32), np.array(val, dtype=np.complex128)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", ["one_row", "empty_rows_C32", "empty_rows_C4", "all_empty_chunk"])
+def test_filter_degenerate_matrices(P, prec, case):
+    """A 1 x 1 matrix, and matrices with rows that store no entry (whole SELL
+    chunks of width 0 among them): the filter must still match the oracle."""
+    if case == "one_row":
+        H = _csr_from_entries(1, [(0, 0, 0.5)])
+        n_b, n_s, C, sigma = 1, 1, 32, 256
+    elif case == "all_empty_chunk":
+        # rows 0..31 empty (a whole chunk of width 0), rows 32..40 a small chain
+        ent = [(i, i + 1, 0.3 + 0.1j) for i in range(32, 40)] + [(i, i, 0.05 * (i - 36)) for i in range(32, 41)]
+        H = _csr_from_entries(41, ent)
+        n_b, n_s, C, sigma = 4, 8, 32, 1
+    else:
+        n = 37
+        ent = [(i, i, 0.2 * np.sin(i)) for i in range(0, n, 2)]
+        ent += [(i, i + 3, 0.25 - 0.15j) for i in range(0, n - 3, 5)]
+        H = _csr_from_entries(n, ent)
+        n_b, n_s = 4, 8
+        C, sigma = (32, 256) if case == "empty_rows_C32" else (4, 1)
+    n = len(H[0]) - 1
+    assert case == "one_row" or np.any(np.diff(H[0]) == 0)
+    n_p = 20
+    X = random_phase_block(n, n_s, 3)
+    Y, eta, nu, al, be, gam, _ = _run_filter(P, H, prec, n_b, n_s, n_p, X, lam=(-0.3, 0.2), C=C, sigma=sigma,
+                                             bounds=(-1.0, 1.0))
+    Yr, etar, nur = O.chebyshev_filter(H, al, be, gam, X, n_b)
+    u = EPS64 if prec == 0 else EPS32
+    tol_T = _bound(n_p, 13, u, 0.9)
+    assert np.max(np.abs(Y - Yr)) <= max(np.sum(np.abs(gam)), 1.0) * tol_T
+    tol_m = 2.0 * n * tol_T + n * 4 * u
+    assert np.max(np.abs(eta[1:] - etar[1:])) <= tol_m
+    assert np.max(np.abs(nu[1:] - nur[1:].real)) <= tol_m
