@@ -116,6 +116,20 @@ def grid(heur_np: int, heur_ns: int):
     return [(a, b) for a in nps for b in nss]
 
 
+def next_adaptive_np(n_p: int, found: list, np_cap: int):
+    """The next filter degree of the adaptive label search, or None to stop.
+
+    The search doubles n_p while no run has converged with pairs; it stops at
+    np_cap, and once a doubling found no more pairs than the run before it
+    (that instance's window is not resolved by a higher degree within the
+    iteration limit: its subspace or its interval is the problem)."""
+    if 2 * n_p > np_cap:
+        return None
+    if len(found) >= 2 and found[-1] > 0 and found[-1] <= found[-2]:
+        return None
+    return 2 * n_p
+
+
 def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, count_range=None, log=print,
                 adaptive: bool = False, start_np: int = 50, out: str | None = None):
     """Features, heuristic choice, grid runs and labels of `count` instances
@@ -142,16 +156,20 @@ def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, c
                 f"{r.n_found} pairs, {dt:.2f} s")
             return r.status == 0 and r.n_found > 0
         if adaptive:
-            # double n_p from the heuristic's until a run finds pairs, then one more
+            # double n_p from the heuristic's until a run converges with pairs (at
+            # most 8 times the start, see next_adaptive_np), then one more
             # doubling and one wider subspace at that degree
             n_p = max(hp, start_np)
-            while n_p <= _abi.NP_MAX:
+            np_cap = min(_abi.NP_MAX, 8 * n_p)
+            found = []
+            while n_p is not None:
                 if solve(n_p, hs):
                     if 2 * n_p <= _abi.NP_MAX:
                         solve(2 * n_p, hs)
                     solve(n_p, min(512, hs + N_B))
                     break
-                n_p *= 2
+                found.append(results[-1]["n_found"])
+                n_p = next_adaptive_np(n_p, found, np_cap)
         else:
             for n_p, n_s in grid(hp, hs):
                 solve(n_p, n_s)

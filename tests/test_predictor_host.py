@@ -62,3 +62,15 @@ def test_targets_invert_through_choose_params():
         a, b = r["features"][256], r["features"][257]
         assert O.choose_params(a, b, r["count_est"], 32, mlp_out=zz, t_mean=mean, t_std=std) == tuple(r["label"])
     assert PR.kappa_from_corpus(rows) == np.median(T[:, 0])
+
+
+def test_adaptive_search_stops():
+    # doubling while nothing converged, up to the cap
+    assert PR.next_adaptive_np(100, [0], 800) == 200
+    assert PR.next_adaptive_np(400, [0, 0, 0], 800) == 800
+    assert PR.next_adaptive_np(800, [0, 0, 0, 0], 800) is None
+    # pairs found but not converged: keep doubling while the count grows
+    assert PR.next_adaptive_np(200, [0, 12], 1600) == 400
+    assert PR.next_adaptive_np(400, [0, 12, 20], 1600) == 800
+    # a doubling that found no more pairs ends the search
+    assert PR.next_adaptive_np(800, [0, 20, 20], 1600) is None
