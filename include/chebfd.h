@@ -127,8 +127,8 @@ int chebfd_bounds(const chebfd_matrix *H, void *d_work, size_t work_bytes, void 
  * Filter coefficients (host): gamma_p = g_p c_p, p = 0..n_p, where c_p are the
  * Chebyshev coefficients of the indicator of the scaled interval
  * [a, b] = [alpha lam_L + beta, alpha lam_R + beta] (the window function of
- * Sect. 2) and g_p the Jackson damping factors for n_p + 1 terms (Alg. 1,
- * lines 6 and 12 use the products g_p c_p).  Also returns alpha, beta from
+ * Sect. 2) and g_p the Jackson damping factors for n_p + 1 terms (Alg. 1
+ * weights each T_p x with the product g_p c_p).  Also returns alpha, beta from
  * the bounds [lam_lo, lam_hi].  CHEBFD_EINTERVAL unless -1 < a < b < 1.
  */
 int chebfd_coefficients(double lam_lo, double lam_hi, double lam_L, double lam_R,
@@ -192,8 +192,8 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
                   void *stream);
 
 /*
- * One fused Chebyshev step on one block, as timed by the benchmarks (Alg. 1,
- * lines 9-12): W <- 2(alpha H + beta I) U - W in place, eta_p = <W, U>,
+ * One fused Chebyshev step on one block, as timed by the benchmarks (the
+ * recurrence step of Alg. 1): W <- 2(alpha H + beta I) U - W in place, eta_p = <W, U>,
  * mu_p = <U, U>, Y <- Y + gamma W.  Same layouts and workspace as
  * chebfd_filter; the dot products stay in d_work (not reduced).
  */
@@ -202,7 +202,7 @@ int chebfd_op(const chebfd_matrix *H, double alpha, double beta, double gamma, i
               size_t work_bytes, void *stream);
 
 /*
- * Sparse matrix times one block (Alg. 1 line 4, spmmv()): Y = (alpha H + beta I) X
+ * Sparse matrix times one block (the first product of Alg. 1, spmmv()): Y = (alpha H + beta I) X
  * for an n x n_b block in the blocked layout and the matrix's precision.
  * d_work: chebfd_filter_query bytes.  X and Y must not overlap.
  */

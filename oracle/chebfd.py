@@ -91,7 +91,7 @@ def scale_factors(lam_lo: float, lam_hi: float):
 
 
 # ---------------------------------------------------------------------------
-# Filter coefficients g_p c_p (Alg. 1, lines 6 and 12)
+# Filter coefficients g_p c_p (the products that weight each T_p x in Alg. 1)
 # ---------------------------------------------------------------------------
 def window_coefficients(a: float, b: float, n_p: int) -> np.ndarray:
     """Chebyshev coefficients c_0..c_{n_p} of the indicator of [a, b] within [-1, 1].
@@ -154,7 +154,7 @@ def chebyshev_filter(H, alpha: float, beta: float, gamma: np.ndarray, X: np.ndar
 
     Returns (Y, eta, nu): Y the filtered block; eta, nu of shape (n_p + 1, n_s) with
     eta[p] = <T_p x, T_{p-1} x> and nu[p] = <T_{p-1} x, T_{p-1} x> for p >= 1
-    (Alg. 1 lines 10-11 for p >= 3, the same products of the start vectors for
+    (the dot products of Alg. 1's recurrence step for p >= 3, the same products of the start vectors for
     p = 1, 2), row 0 zero.
     """
     lib = load_library()

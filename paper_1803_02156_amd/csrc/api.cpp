@@ -609,7 +609,7 @@ static int filter_run(const chebfd_matrix *H, double alpha, double beta, const d
             continue;
         }
         StepArgs a = base_args(H, alpha, beta);
-        // U <- (aH + bI) X                                         (Alg. 1 line 4)
+        // U <- (aH + bI) X                                         (Alg. 1, first product)
         a.P = X;
         a.N = A;
         if ((rc = launch_any(H, prec, n_b, kModeFirst, next_args(a, 1, b), geo, s))) return rc;
@@ -629,7 +629,7 @@ static int filter_run(const chebfd_matrix *H, double alpha, double beta, const d
             if ((rc = launch_axpby_blocked(prec, count, h_gamma[0], X, h_gamma[1], A, s))) return rc;
             continue;
         }
-        // W <- 2(aH + bI) U - X;  X <- g0c0 X + g1c1 U + g2c2 W         (lines 5-6)
+        // W <- 2(aH + bI) U - X;  X <- g0c0 X + g1c1 U + g2c2 W         (Alg. 1, start of Y)
         a = base_args(H, alpha, beta);
         a.P = A;
         a.O = X;
@@ -639,7 +639,7 @@ static int filter_run(const chebfd_matrix *H, double alpha, double beta, const d
         a.g1 = h_gamma[1];
         a.g2 = h_gamma[2];
         if ((rc = launch_any(H, prec, n_b, kModeSecond, next_args(a, 2, b), geo, s))) return rc;
-        // p = 3..n_p: swap(W, U); chebfd_op(H, U, W, X)                  (lines 7-13)
+        // p = 3..n_p: swap(W, U); chebfd_op(H, U, W, X)                  (Alg. 1, recurrence)
         void *Ub = B, *Wb = A;  // after the swap U holds T_2, W holds T_1
         for (int p = 3; p <= n_p; ++p) {
             a = base_args(H, alpha, beta);

@@ -1,7 +1,7 @@
 // Fused Chebyshev step with the gathered block staged in LDS (gfx950).
 //
-// Same computation as the other step kernels (Alg. 1 lines 9-12 of the ChebFD
-// paper, and the start launches of lines 4-6): per row i and block column j,
+// Same computation as the other step kernels (the recurrence step of Alg. 1 of
+// the ChebFD paper, and its two start launches): per row i and block column j,
 // W_ij <- 2 ((aH + bI) U)_ij - W_ij, the filtered-block update and the
 // per-column dot products.
 //

@@ -8,9 +8,9 @@
 namespace chebfd {
 
 // Variants of the fused step kernel.
-//  kModeFirst : N = (aH+bI) P                                 (Alg. 1 line 4)
-//  kModeSecond: N = 2(aH+bI) P - O;  Y(=O) = g0 O + g1 P + g2 N   (lines 5-6)
-//  kModeStep  : O = 2(aH+bI) P - O (in place);  Y += g2 O       (lines 9-12)
+//  kModeFirst : N = (aH+bI) P                                 (Alg. 1, first product)
+//  kModeSecond: N = 2(aH+bI) P - O;  Y(=O) = g0 O + g1 P + g2 N   (Alg. 1, start of Y)
+//  kModeStep  : O = 2(aH+bI) P - O (in place);  Y += g2 O       (Alg. 1, recurrence step)
 //  kModeKpm   : O = 2(aH+bI) P - O (in place), no Y update      (moments only)
 // Every mode also forms the per-column products <new, P> and <P, P>.
 enum { kModeFirst = 0, kModeSecond = 1, kModeStep = 2, kModeKpm = 3 };

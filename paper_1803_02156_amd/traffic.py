@@ -23,7 +23,7 @@ def step_bytes(n: int, nnz: int, n_b: int, prec: int) -> tuple[int, int]:
 
 
 def start_bytes(n: int, nnz: int, n_b: int, prec: int) -> tuple[int, int]:
-    """(read, write) of the two start launches (Alg. 1 lines 4-6): U = H~X; W = 2H~U - X, X = ..."""
+    """(read, write) of the two start launches (the start of Alg. 1): U = H~X; W = 2H~U - X, X = ..."""
     s = value_bytes(prec)
     first = (nnz * (s + 4) + n * n_b * s, n * n_b * s)
     second = (nnz * (s + 4) + 2 * n * n_b * s, 2 * n * n_b * s)
