@@ -344,6 +344,8 @@ typedef struct chebfd_predictor {
     double kappa;           /* heuristic: n_p = kappa / delta */
     double t_mean[2];       /* MLP output de-standardisation: log(n_p delta), log(n_s / max(2 n_hat, n_b)) */
     double t_std[2];
+    double t_lo[2];         /* de-standardised outputs are clamped to [t_lo, t_hi] (the range of the */
+    double t_hi[2];         /* training targets) where t_lo < t_hi; t_lo = t_hi = 0: no clamp */
 } chebfd_predictor;
 
 /*
@@ -366,7 +368,8 @@ int chebfd_features(const chebfd_matrix *H, double lam_L, double lam_R, uint64_t
  * (n_p, n_s) from the scaled interval [a, b], the count estimate and either the
  * MLP's two outputs (h_mlp_out, host: standardised log(n_p delta) and
  * log(n_s / max(2 n_hat, n_b)), so n_p = exp(t_std[0] y0 + t_mean[0]) / delta
- * and n_s = exp(t_std[1] y1 + t_mean[1]) max(2 n_hat, n_b)) or, with h_mlp_out NULL,
+ * and n_s = exp(t_std[1] y1 + t_mean[1]) max(2 n_hat, n_b), each exponent first
+ * clamped to [t_lo, t_hi] when that range is set) or, with h_mlp_out NULL,
  * the heuristic.  Both are clamped: n_p to
  * [CHEBFD_NP_MIN, CHEBFD_NP_MAX]; n_s to a multiple of n_b that is at least
  * max(n_b, 1.2 n_hat) and at most 512.  Host only, no device work.

@@ -207,7 +207,8 @@ def count_estimate(mu: np.ndarray, n: int, a: float, b: float) -> float:
 
 
 def choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, kappa: float = 1.0,
-                  t_mean=(0.0, 0.0), t_std=(1.0, 1.0), np_min=50, np_max=20000, ns_max=512):
+                  t_mean=(0.0, 0.0), t_std=(1.0, 1.0), np_min=50, np_max=20000, ns_max=512,
+                  t_lo=(0.0, 0.0), t_hi=(0.0, 0.0)):
     """(n_p, n_s) for the scaled interval [a, b] and a count estimate.
 
     The paper picks n_s a bit above the number of wanted eigenpairs (Sect. 2)
@@ -216,7 +217,8 @@ def choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, 
     scaled variable, so n_p = kappa / delta with delta = (b - a) / 2, and
     n_s = 2 n_hat rounded up to a block.  A network may instead give two
     scale-free ratios, standardised: log(n_p delta) (its own kappa) and
-    log(n_s / max(2 n_hat, n_b)) (its factor on the heuristic's n_s); n_s then
+    log(n_s / max(2 n_hat, n_b)) (its factor on the heuristic's n_s), each held
+    to [t_lo, t_hi] (the training targets' range) when t_lo < t_hi; n_s then
     stays at least 1.2 n_hat.
     Clamped: n_p in [np_min, np_max], n_s a multiple of n_b in [n_b, ns_max].
     """
@@ -226,9 +228,10 @@ def choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, 
         np_real = kappa / delta
         ns_real = 2.0 * nhat
     else:
-        np_real = math.exp(min(30.0, float(mlp_out[0]) * t_std[0] + t_mean[0])) / delta
-        ns_real = max(math.exp(min(30.0, float(mlp_out[1]) * t_std[1] + t_mean[1])) * max(2.0 * nhat, n_b),
-                      1.2 * nhat)
+        y = [min(30.0, float(mlp_out[k]) * t_std[k] + t_mean[k]) for k in (0, 1)]
+        y = [min(t_hi[k], max(t_lo[k], y[k])) if t_lo[k] < t_hi[k] else y[k] for k in (0, 1)]
+        np_real = math.exp(y[0]) / delta
+        ns_real = max(math.exp(y[1]) * max(2.0 * nhat, n_b), 1.2 * nhat)
     n_p = int(min(np_max, max(np_min, math.floor(np_real + 0.5))))   # halves round up
     n_s = int(math.ceil(ns_real / n_b) * n_b)
     n_s = min(max(n_s, n_b), max(n_b, ns_max // n_b * n_b))

@@ -37,7 +37,7 @@ class ChebfdParams(ctypes.Structure):
 
 
 class ChebfdPredictor(ctypes.Structure):
-    _fields_ = [("kappa", f64), ("t_mean", f64 * 2), ("t_std", f64 * 2)]
+    _fields_ = [("kappa", f64), ("t_mean", f64 * 2), ("t_std", f64 * 2), ("t_lo", f64 * 2), ("t_hi", f64 * 2)]
 
 
 class ChebfdStats(ctypes.Structure):

@@ -326,12 +326,15 @@ def chebfd_features(H: Matrix, lam_L: float, lam_R: float, seed: int = 0):
 
 
 def chebfd_choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, kappa: float = 1.0,
-                         t_mean=(0.0, 0.0), t_std=(1.0, 1.0)):
-    """(n_p, n_s) from the heuristic (mlp_out None) or the network's two outputs (host only)."""
+                         t_mean=(0.0, 0.0), t_std=(1.0, 1.0), t_lo=(0.0, 0.0), t_hi=(0.0, 0.0)):
+    """(n_p, n_s) from the heuristic (mlp_out None) or the network's two outputs (host only);
+    t_lo, t_hi: the range the de-standardised outputs are held to (unset when equal)."""
     pr = _abi.ChebfdPredictor()
     pr.kappa = kappa
     pr.t_mean[0], pr.t_mean[1] = t_mean
     pr.t_std[0], pr.t_std[1] = t_std
+    pr.t_lo[0], pr.t_lo[1] = t_lo
+    pr.t_hi[0], pr.t_hi[1] = t_hi
     out = None
     if mlp_out is not None:
         out = np.ascontiguousarray(np.asarray(mlp_out, dtype=np.float32)[:2])

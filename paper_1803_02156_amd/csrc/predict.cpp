@@ -86,9 +86,15 @@ int chebfd_choose_params(double a, double b, double count_est, int32_t n_b, cons
         // the network's outputs: standardised log(n_p delta) and log(n_s / max(2 n_hat, n_b))
         CHEBFD_REQUIRE(std::isfinite(h_mlp_out[0]) && std::isfinite(h_mlp_out[1]), "MLP output not finite");
         CHEBFD_REQUIRE(pr->t_std[0] > 0.0 && pr->t_std[1] > 0.0, "predictor scales must be positive");
-        np_real = std::exp(std::min(30.0, h_mlp_out[0] * pr->t_std[0] + pr->t_mean[0])) / delta;
-        ns_real = std::exp(std::min(30.0, h_mlp_out[1] * pr->t_std[1] + pr->t_mean[1])) *
-                  std::max(2.0 * nhat, static_cast<double>(n_b));
+        // a network asked far outside its training range extrapolates: its outputs
+        // are held to the range of the training targets
+        double y[2];
+        for (int k = 0; k < 2; ++k) {
+            y[k] = std::min(30.0, h_mlp_out[k] * pr->t_std[k] + pr->t_mean[k]);
+            if (pr->t_lo[k] < pr->t_hi[k]) y[k] = std::min(pr->t_hi[k], std::max(pr->t_lo[k], y[k]));
+        }
+        np_real = std::exp(y[0]) / delta;
+        ns_real = std::exp(y[1]) * std::max(2.0 * nhat, static_cast<double>(n_b));
         ns_real = std::max(ns_real, 1.2 * nhat);
     } else {
         CHEBFD_REQUIRE(pr->kappa > 0.0, "kappa must be positive");

@@ -250,16 +250,26 @@ def predict(params: np.ndarray, features: np.ndarray) -> np.ndarray:
     return P.chebfd_mlp_forward(p, x).cpu().numpy()
 
 
-def save(path: str, params: np.ndarray, mean, std, kappa: float, meta: dict):
+def target_range(T: np.ndarray):
+    """(t_lo, t_hi): the range of the log targets, to which the parameter rule
+    holds the network's outputs (a network asked far outside it extrapolates)."""
+    lg = np.log(T.astype(np.float64))
+    return tuple(lg.min(axis=0)), tuple(lg.max(axis=0))
+
+
+def save(path: str, params: np.ndarray, mean, std, kappa: float, meta: dict, t_lo=(0.0, 0.0),
+         t_hi=(0.0, 0.0)):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     np.savez(path, params=params.astype(np.float32), t_mean=np.asarray(mean), t_std=np.asarray(std),
-             kappa=np.asarray(kappa), meta=np.asarray(json.dumps(meta)))
+             kappa=np.asarray(kappa), meta=np.asarray(json.dumps(meta)), t_lo=np.asarray(t_lo),
+             t_hi=np.asarray(t_hi))
 
 
 def load(path: str = DEFAULT_WEIGHTS):
     z = np.load(path, allow_pickle=False)
+    rng = (tuple(z["t_lo"]), tuple(z["t_hi"])) if "t_lo" in z.files else ((0.0, 0.0), (0.0, 0.0))
     return dict(params=z["params"], t_mean=tuple(z["t_mean"]), t_std=tuple(z["t_std"]),
-                kappa=float(z["kappa"]), meta=json.loads(str(z["meta"])))
+                kappa=float(z["kappa"]), meta=json.loads(str(z["meta"])), t_lo=rng[0], t_hi=rng[1])
 
 
 def choose(pred: dict | None, features: np.ndarray, count_est: float, kappa: float):
@@ -269,7 +279,8 @@ def choose(pred: dict | None, features: np.ndarray, count_est: float, kappa: flo
         return P.chebfd_choose_params(a, b, count_est, N_B, kappa=kappa)
     out = predict(pred["params"], features)[0]
     return P.chebfd_choose_params(a, b, count_est, N_B, out, kappa=kappa, t_mean=pred["t_mean"],
-                                  t_std=pred["t_std"])
+                                  t_std=pred["t_std"], t_lo=pred.get("t_lo", (0.0, 0.0)),
+                                  t_hi=pred.get("t_hi", (0.0, 0.0)))
 
 
 def evaluate(pred: dict, corpus: list, kappa: float, log=print):
@@ -374,11 +385,13 @@ def main(argv=None):
         rows = [r for p in a.corpus for r in json.load(open(p)) if r["label"] is not None and r["full_count"] > 0]
         X = np.array([features_of(r) for r in rows], dtype=np.float32)
         T, mean, std = standardise(targets(rows))
+        t_lo, t_hi = target_range(targets(rows))
         kappa = kappa_from_corpus(rows) if a.kappa is None else a.kappa
         params = train(X, T, steps=a.steps, log=log)
         save(a.out, params, mean, std, kappa, {"train_instances": len(rows), "steps": a.steps,
                                                "targets": "log(n_p delta), log(n_s / max(2 n_hat, n_b))",
-                                               "corpus": [os.path.basename(p) for p in a.corpus]})
+                                               "corpus": [os.path.basename(p) for p in a.corpus]},
+             t_lo=t_lo, t_hi=t_hi)
         log(f"# kappa {kappa:.3f}")
         log(f"# saved {a.out}")
     elif a.cmd == "eval":

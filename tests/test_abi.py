@@ -101,10 +101,13 @@ def test_probe_rejects_bad_args(lib):
     (-1e-6, 1e-6, -2.0, 8, None), (-0.02, 0.05, 10.0, 32, (0.3, -1.2)), (-0.02, 0.05, 400.0, 64, (9.0, 9.0)),
     (-0.5, 0.5, 0.0, 128, (-40.0, -40.0)),
 ])
-def test_choose_params_matches_oracle(a, b, cnt, n_b, out):
+@pytest.mark.parametrize("clamp", [None, ((1.0, -0.5), (3.0, 0.9))])
+def test_choose_params_matches_oracle(a, b, cnt, n_b, out, clamp):
     import paper_1803_02156_amd as P
     import oracle as O
     kw = dict(kappa=1.7, t_mean=(6.0, 4.0), t_std=(1.3, 0.8))
+    if clamp is not None:
+        kw.update(t_lo=clamp[0], t_hi=clamp[1])
     got = P.chebfd_choose_params(a, b, cnt, n_b, out, **kw)
     if out is not None:
         out = np.asarray(out, dtype=np.float32)

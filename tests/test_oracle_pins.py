@@ -316,3 +316,9 @@ def test_choose_params_reading():
     assert n_p == 500 and n_s == 320                                            # 20 / 0.04, 1.5 x 200
     n_p, n_s = O.choose_params(-0.1, 0.1, 3.0, 32, mlp_out=(0.0, 0.0), t_mean=(np.log(20.0), np.log(1.5)))
     assert n_p == 200 and n_s == 64                                             # 2 n_hat < n_b: 1.5 x 32
+    # outputs held to the training range [t_lo, t_hi] of the log targets
+    kw = dict(t_mean=(np.log(20.0), np.log(1.5)), t_std=(1.0, 1.0), t_lo=(np.log(5.0), 0.0),
+              t_hi=(np.log(50.0), np.log(2.0)))
+    assert O.choose_params(-0.1, 0.1, 100.0, 32, mlp_out=(5.0, 5.0), **kw) == (500, 416)     # 50 / 0.1, 2 x 200
+    assert O.choose_params(-0.1, 0.1, 100.0, 32, mlp_out=(-5.0, -5.0), **kw) == (50, 224)   # 5 / 0.1; 1 x 200
+    assert O.choose_params(-0.1, 0.1, 100.0, 32, mlp_out=(0.0, 0.0), **kw) == (200, 320)    # inside: unchanged

@@ -74,3 +74,9 @@ def test_adaptive_search_stops():
     assert PR.next_adaptive_np(400, [0, 12, 20], 1600) == 800
     # a doubling that found no more pairs ends the search
     assert PR.next_adaptive_np(800, [0, 20, 20], 1600) is None
+
+
+def test_target_range_is_the_span_of_the_log_targets():
+    T = np.array([[10.0, 1.0], [20.0, 2.5], [5.0, 1.2]])
+    lo, hi = PR.target_range(T)
+    assert np.allclose(lo, np.log([5.0, 1.0])) and np.allclose(hi, np.log([20.0, 2.5]))
