@@ -1,19 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the ChebFD polynomial filter on one MI355X.
 
-One step = one full filter application (Alg. 1 on every block, Alg. 2 over the
-blocks) to an n_s-vector search block of the Topi-64-64-32 lattice Hamiltonian
-(n = 524288, 13 non-zeros per row, disorder W = 1, complex double,
-SELL-32-256), n_s = 256 in blocks of n_b = 32, filter degree n_p = 1000.
-Inputs are synthetic and resident in HBM before the timed region.
+Headline workload: the Topi-256-256-128 lattice Hamiltonian (n = 33554432,
+13 non-zeros per row, m = 1, disorder W = 1, complex double, SELL-32-256,
+lattice row order), the largest configuration one GPU holds.  One step = the
+filter polynomial of degree n_p = 100 applied to one block of n_b = 32 search
+vectors (Alg. 1: two start launches and n_p - 2 fused chebfd_op steps, with
+the dot products and the filtered-block update), from a fresh random-phase
+start block.  The n_s = 256 search space is 8 such blocks, which are
+independent (Alg. 2).  Inputs are synthetic and resident in HBM before the
+timed region.
 
-Prints one JSON line: the filter's algorithmic HBM bandwidth (the paper's
-minimum-traffic model, Sect. 3.4) as `value`, the roofline of the fused step
-kernel (its launches timed on their own), the same filter with c64 block
-vectors (`filter_mixed`), the time to converged Ritz pairs of the whole
-iteration in FP64, in mixed precision and in mixed precision with the learned
-(n_p, n_s) on the same matrix, and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+Prints one JSON line: `value` = the paper's minimum-traffic bytes of the
+filter (Sect. 3.4, Eq. 2) per second; the roofline of the fused step kernel
+(its average launch over the timed region, HIP events on the launch stream);
+the unfused filter on the same block (SpMMV, dot and axpby as separate calls,
+the GHOST-nofuse comparison of Sect. 3.2); the same filter with c64 block
+vectors; the FP64 MFMA Gram product Y^H Y of a 256-vector search space; the
+time to converged Ritz pairs on the 64x64x32 lattice in FP64 and mixed
+precision with the heuristic's (n_p, n_s) and in mixed precision with the
+learned (n_p, n_s); and the FP64 CPU oracle timed on bounded samples on the
+host cores.
 """
 from __future__ import annotations
 
@@ -21,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -30,33 +38,39 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+FP64_MFMA_PEAK_TFLOPS = 78.6
 METRIC = "Cheb filter HBM GB/s (% of peak); time to converged pairs, plain vs mixed"
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--lattice", type=str, default="64x64x32")
+    ap.add_argument("--lattice", type=str, default="256x256x128")
     ap.add_argument("--W", type=float, default=1.0)
-    ap.add_argument("--n_s", type=int, default=256)
     ap.add_argument("--n_b", type=int, default=32)
-    ap.add_argument("--n_p", type=int, default=1000)
+    ap.add_argument("--n_p", type=int, default=100)
     ap.add_argument("--prec", type=int, default=0, help="0 = FP64, 1 = mixed (c64 storage)")
-    ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
-                    help="target CPU time of the oracle sample (0 disables)")
-    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-converged leg")
-    ap.add_argument("--no-mixed-filter", action="store_true",
-                    help="skip the c64 filter leg (timed after the FP64 filter when --prec 0)")
-    ap.add_argument("--solve-prec", choices=("both", "fp64", "mixed"), default="both",
-                    help="precisions of the time-to-converged leg")
+    ap.add_argument("--order", choices=("lattice", "natural"), default="lattice",
+                    help="row order at ingest: lattice boxes/pencils (one box per XCD) or the natural order")
+    ap.add_argument("--op-launches", type=int, default=20, help="launches of the fused step timed alone")
+    ap.add_argument("--no-unfused", action="store_true", help="skip the unfused filter leg")
+    ap.add_argument("--mixed-n_b", type=int, default=32, help="block width of the c64 filter leg (0 skips it)")
+    ap.add_argument("--gram-n_s", type=int, default=256, help="search-space size of the Gram leg (0 skips it)")
+    ap.add_argument("--solve-lattice", type=str, default="64x64x32",
+                    help="lattice of the time-to-converged leg ('' skips it)")
+    ap.add_argument("--solve-W", type=float, default=1.0)
     ap.add_argument("--solve-count", type=float, default=100.0,
                     help="eigenvalue count the symmetric search interval is sized for")
-    ap.add_argument("--op-launches", type=int, default=200, help="launches of the fused step timed alone")
-    ap.add_argument("--order", choices=("lattice", "natural"), default="lattice",
-                    help="row order at ingest: lattice boxes/slabs (one box per XCD) or the natural order")
+    ap.add_argument("--solve-n_b", type=int, default=32)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
+                    help="target CPU time of each oracle sample (0 disables)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 # fused-step kernels (chebfd_step_kernel kinds): short name, source file
@@ -65,9 +79,9 @@ STEP_KERNELS = {0: ("cheb_lds", "filter_lds.hip"), 1: ("cheb_row", "filter_rows.
 
 
 def kernel_source_hash(kind: int) -> str:
-    """Hash of the step kernel's source and the pack header it includes."""
+    """Hash of the step kernel's source and the headers it includes."""
     h = hashlib.sha256()
-    for name in (STEP_KERNELS[kind][1], "step_io.h"):
+    for name in (STEP_KERNELS[kind][1], "step_io.h", "kernels.h"):
         with open(os.path.join(HERE, "paper_1803_02156_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -88,53 +102,57 @@ def counter_traffic(kind: int, prec: int, n_b: int, lattice: str, order: str):
     return t["hbm_bytes_per_launch"]
 
 
-def mixed_filter_leg(P, H, order, lattice, order_name, n_s, n_b, n_p, steps):
-    """The same full filter with c64 block vectors and a c64 matrix (the mixed
-    precision's filter stage): algorithmic GB/s, the fused step's average launch
-    and the step kernel with its committed HBM traffic."""
-    import torch
-    from paper_1803_02156_amd import traffic
-    from topi import random_phase_block
-    n, nnz = len(H[0]) - 1, len(H[1])
-    M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=1, order=order)
-    lo, hi = P.chebfd_bounds(M)
-    al, be, gam = P.chebfd_coefficients(lo, hi, -0.1, 0.1, n_p)
-    X0 = random_phase_block(n, n_s, 45)
-    x0 = torch.empty((n_s, n), dtype=torch.complex128, device="cuda")
-    x0.copy_(torch.from_numpy(np.ascontiguousarray(X0.T)))
-    del X0
-    xb0 = P.chebfd_pack(M, x0.T, n_b)
-    del x0
-    xy = torch.empty_like(xb0)
-    work = P.FilterWork(M, n_b, n_p, n_s, moments=True)
-    stream = torch.cuda.current_stream()
+class BlockFilter:
+    """One n_b-vector block of the lattice matrix M: a device start block, a work
+    block and timed filter applications (restore the start block, then filter)."""
 
-    def step():
-        xy.copy_(xb0)
-        P.chebfd_filter(M, al, be, gam, n_s, n_b, xy, work=work)
-    step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    gbs = traffic.filter_bytes(n, nnz, n_s, n_b, n_p, 1) / (ms * 1e-3) / 1e9
-    avg_launch_s = ms * 1e-3 / ((n_s // n_b) * n_p)
-    r, w = traffic.step_bytes(n, nnz, n_b, 1)
-    kind = P.chebfd_step_kernel(M, n_b)
-    out = {"value": round(gbs, 2), "unit": "GB/s", "ms_per_filter": round(ms, 3),
-           "pct_of_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
-           "kernel": f"{STEP_KERNELS[kind][0]}_kernel<float,{n_b},kModeStep>",
-           "avg_launch_us": round(avg_launch_s * 1e6, 3), "bytes_per_launch": r + w,
-           "frac": round((r + w) / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4),
-           "traffic": counter_traffic(kind, 1, n_b, lattice, order_name),
-           "kernel_source_sha256_16": kernel_source_hash(kind)}
-    del xy, xb0, work, M
-    torch.cuda.empty_cache()
-    return out
+    def __init__(self, P, M, n_b, n_p, lam=0.1, seed=44):
+        import torch
+        self.P, self.M, self.n_b, self.n_p = P, M, n_b, n_p
+        lo, hi = P.chebfd_bounds(M)
+        self.bounds = (lo, hi)
+        # search interval [-lam, lam] in H's units (the filter's cost does not depend on it)
+        self.al, self.be, self.gam = P.chebfd_coefficients(lo, hi, -lam, lam, n_p)
+        self.x0 = P.chebfd_random_phase(M, n_b, n_b, seed)
+        self.xy = torch.empty_like(self.x0)
+        self.work = P.FilterWork(M, n_b, n_p, n_b, moments=True)
+        self.stream = torch.cuda.current_stream()
+
+    def run(self, steps, unfused=False):
+        """Time `steps` steps; returns (ms per step, ms of the filter calls alone per step)."""
+        import torch
+        P = self.P
+        fn = P.chebfd_filter_unfused if unfused else P.chebfd_filter
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(self.stream)
+        for k in range(steps):
+            self.xy.copy_(self.x0)   # fresh start block (the filter overwrites X by Y)
+            ev[k][0].record(self.stream)
+            fn(self.M, self.al, self.be, self.gam, self.n_b, self.n_b, self.xy, work=self.work)
+            ev[k][1].record(self.stream)
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        total = e0.elapsed_time(e1) / steps
+        filt = sum(a.elapsed_time(b) for a, b in ev) / steps
+        return total, filt
+
+    def op_alone(self, launches):
+        """Average duration of `launches` back-to-back chebfd_op launches (the Step kernel)."""
+        import torch
+        P = self.P
+        opw = P.device_buffer(P.chebfd_filter_query(self.M, self.n_b))
+        u, w, y = self.work.u, self.work.w, self.xy.view(self.M.n, self.n_b)
+        P.chebfd_op(self.M, self.al, self.be, self.gam[3], self.n_b, u, w, y, opw, opw.numel())
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        for _ in range(launches):
+            P.chebfd_op(self.M, self.al, self.be, self.gam[3], self.n_b, u, w, y, opw, opw.numel())
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / launches
 
 
 def interval_for_count(P, M, target, seed=7, n_steps=1024, R=16):
@@ -161,105 +179,136 @@ def interval_for_count(P, M, target, seed=7, n_steps=1024, R=16):
     return 0.5 * (a + b), count(0.5 * (a + b))
 
 
-def time_to_converged(P, H, Nx, Ny, Nz, W, n_s, n_b, n_p, target, order, which="both"):
-    """Full ChebFD runs (filter, SVQB, Rayleigh-Ritz, residuals, restarts) in FP64 and
-    mixed precision on the same matrix and interval; wall time from the first launch
-    to the synchronised end, matrix build excluded."""
+def time_to_converged(P, lattice, W, n_b, target):
+    """Full ChebFD runs (filter, SVQB, Rayleigh-Ritz, residuals, restarts) on one
+    matrix and interval: FP64 and mixed precision with the heuristic's (n_p, n_s)
+    (the fallback rule), and mixed precision with the learned (n_p, n_s).  Wall
+    time from the first launch to the synchronised end; matrix build excluded."""
     import torch
+    from paper_1803_02156_amd import predictor as PR
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    from topi import topi_csr
+    Nx, Ny, Nz = (int(v) for v in lattice.split("x"))
+    H = topi_csr(Nx, Ny, Nz, m=1.0, W=W, t=1.0, seed=1002)
+    order = lattice_row_order(Nx, Ny, Nz)
     M64 = P.chebfd_matrix_build(*H, prec=0, order=order)
+    M32 = P.chebfd_matrix_build(*H, prec=1, order=order)
     delta, cnt = interval_for_count(P, M64, target)
-    out = {"workload": f"Topi-{Nx}-{Ny}-{Nz} (W={W}), interval [-{delta:.6g}, {delta:.6g}] "
-                       f"(KPM count estimate {cnt:.1f}, 2048 moments), n_s={n_s}, n_b={n_b}, n_p={n_p}",
-           "interval": [-delta, delta], "count_est_kpm": cnt}
+    pred = PR.load(PR.DEFAULT_WEIGHTS)
+    f, cnt_f, _, _ = P.chebfd_features(M64, -delta, delta, 7)
+    hp, hs = PR.choose(None, f, cnt_f, pred["kappa"])
+    lp, ls = PR.choose(pred, f, cnt_f, pred["kappa"])
+    out = {"workload": f"Topi-{Nx}-{Ny}-{Nz} (n={M64.n}, W={W}), interval [-{delta:.6g}, {delta:.6g}] "
+                       f"(KPM count estimate {cnt:.1f}, 2048 moments), n_b={n_b}, max 12 iterations",
+           "interval": [-delta, delta], "count_est_kpm": cnt, "count_est_features": cnt_f,
+           "heuristic": {"n_p": hp, "n_s": hs, "kappa": pred["kappa"]}, "learned": {"n_p": lp, "n_s": ls}}
     runs = {}
-    for name, prec in (("fp64", 0), ("mixed", 1)):
-        if which not in ("both", name):
-            continue
-        M = M64 if prec == 0 else P.chebfd_matrix_build(*H, prec=1, order=order)
+    for name, M, n_p, n_s in (("fp64_heuristic", M64, hp, hs), ("mixed_heuristic", M32, hp, hs),
+                              ("mixed_learned", M32, lp, ls)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = P.chebfd_solve(M, M64, -delta, delta, n_s, n_p, n_b, seed=43, max_iter=12, want_vectors=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        nf = r.n_found
+        nf, st = r.n_found, r.stats
         runs[name] = r
-        st = r.stats
         out[name] = {
             "seconds": round(dt, 3), "status": r.status, "iterations": st.iterations, "n_found": nf,
-            "max_resid": float(np.max(r.resid[:nf])) if nf else None,
-            "tol": 1e-9 if prec == 0 else 1e-7,
+            "n_p": n_p, "n_s": n_s, "max_resid": float(np.max(r.resid[:nf])) if nf else None,
+            "tol": 1e-9 if M is M64 else 1e-7,
             "t_filter": round(st.t_filter, 3), "t_orth": round(st.t_orth, 3), "t_rr": round(st.t_rr, 3),
             "t_resid": round(st.t_resid, 3),
             "filter_gbs": round(st.filter_bytes / st.t_filter / 1e9, 1) if st.t_filter > 0 else None,
         }
-        print(f"# solve {name}: {dt:.2f} s, status {r.status}, {st.iterations} iterations, "
-              f"{nf} pairs", file=sys.stderr, flush=True)
-        del M
-    if which == "both":
-        # mixed precision with the trained predictor's (n_p, n_s) for this matrix and interval
-        from paper_1803_02156_amd import predictor as PR
-        if os.path.exists(PR.DEFAULT_WEIGHTS):
-            pred = PR.load(PR.DEFAULT_WEIGHTS)
-            f, cnt, _, _ = P.chebfd_features(M64, -delta, delta, 7)
-            lp, ls = PR.choose(pred, f, cnt, pred["kappa"])
-            ls = max(n_b, ls // n_b * n_b)
-            M = P.chebfd_matrix_build(*H, prec=1, order=order)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = P.chebfd_solve(M, M64, -delta, delta, ls, lp, n_b, seed=43, max_iter=12, want_vectors=False)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            nf = r.n_found
-            out["mixed_learned"] = {"seconds": round(dt, 3), "status": r.status, "iterations": r.stats.iterations,
-                                    "n_found": nf, "n_p": lp, "n_s": ls,
-                                    "max_resid": float(np.max(r.resid[:nf])) if nf else None}
-            print(f"# solve mixed + learned (n_p {lp}, n_s {ls}): {dt:.2f} s, status {r.status}, "
-                  f"{r.stats.iterations} iterations, {nf} pairs", file=sys.stderr, flush=True)
-            del M
-    if len(runs) == 2:
-        a, b = runs["fp64"], runs["mixed"]
-        if a.n_found == b.n_found and a.n_found > 0:
-            out["mixed"]["max_abs_dtheta_vs_fp64"] = float(np.max(np.abs(np.sort(a.theta[:a.n_found]) -
-                                                                          np.sort(b.theta[:b.n_found]))))
-        out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
-        ml = out.get("mixed_learned")
-        if ml is not None:
-            ok = ml["status"] == 0 and ml["n_found"] >= a.n_found
-            ml["converged_all_pairs"] = ok
-            # a speedup only for a run that found every pair the FP64 run found
-            out["speedup_mixed_learned_vs_fp64"] = round(out["fp64"]["seconds"] / ml["seconds"], 3) if ok else None
-    return out
+        log(f"solve {name} (n_p {n_p}, n_s {n_s}): {dt:.2f} s, status {r.status}, {st.iterations} iterations, "
+            f"{nf} pairs")
+    ref = runs["fp64_heuristic"]
+    for name in ("mixed_heuristic", "mixed_learned"):
+        r = runs[name]
+        o = out[name]
+        o["all_pairs_of_fp64_run"] = bool(r.status == 0 and ref.status == 0 and r.n_found >= ref.n_found > 0)
+        if r.n_found == ref.n_found and r.n_found > 0:
+            o["max_abs_dtheta_vs_fp64"] = float(np.max(np.abs(np.sort(r.theta[:r.n_found]) -
+                                                             np.sort(ref.theta[:ref.n_found]))))
+        o["speedup_vs_fp64_heuristic"] = round(out["fp64_heuristic"]["seconds"] / o["seconds"], 3)
+    del M64, M32
+    return out, H
 
 
-def oracle_sample(H, n, nnz, n_b, prec, target_s):
-    """Time the FP64 CPU oracle (unfused Alg. 1) on one block of n_b vectors for a few
-    degree steps; returns its algorithmic GB/s under the same byte model."""
+def cpu_info():
+    model = platform.processor() or None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_filter_rate(H, n_b, target_s, threads=None):
+    """The FP64 CPU oracle (unfused Alg. 1) on one block of n_b vectors for a few
+    degree steps of the given matrix; its rate under the same byte model."""
     import oracle as O
     from topi import random_phase_block
     from paper_1803_02156_amd import traffic
 
     lib = O.load_library()
-    X = random_phase_block(n, n_b, 4242)
-    lo, hi = O.gershgorin_bounds(H)
-    al, be = O.scale_factors(lo, hi)
-    # calibrate: a degree-4 filter, then scale the degree to the time budget
+    nthreads0 = lib.orc_num_threads()
+    if threads:
+        lib.orc_set_num_threads(threads)
+    try:
+        n, nnz = len(H[0]) - 1, len(H[1])
+        X = random_phase_block(n, n_b, 4242)
+        lo, hi = O.gershgorin_bounds(H)
+        al, be = O.scale_factors(lo, hi)
+        # calibrate with a degree-3 filter, then scale the degree to the time budget
+        t0 = time.perf_counter()
+        O.chebyshev_filter(H, al, be, np.ones(4), X, n_b)
+        per_step = max((time.perf_counter() - t0) / 3.0, 1e-6)
+        n_p = int(max(3, min(400, target_s / per_step)))
+        t0 = time.perf_counter()
+        O.chebyshev_filter(H, al, be, np.ones(n_p + 1), X, n_b)
+        dt = time.perf_counter() - t0
+        nbytes = traffic.filter_bytes(n, nnz, n_b, n_b, n_p, 0)
+        used = lib.orc_num_threads()
+    finally:
+        lib.orc_set_num_threads(nthreads0)
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(used), "seconds": round(dt, 2),
+            "n_p": n_p, "gflops": traffic.filter_flops(n, n_b, n_p, nnz / n) / dt / 1e9}
+
+
+def oracle_small_solve():
+    """Time to converged pairs of the oracle's full FP64 solve on the 16x16x8
+    configuration (interval [-0.05, 0.05], n_s = n_b = 32, n_p = 200)."""
+    import oracle as O
+    from topi import random_phase_block, topi_csr
+    H = topi_csr(16, 16, 8, m=1.0, W=1.0, seed=1001)
+    X0 = random_phase_block(8192, 32, 43)
     t0 = time.perf_counter()
-    O.chebyshev_filter(H, al, be, np.ones(5), X, n_b)
-    t4 = time.perf_counter() - t0
-    per_step = max(t4 / 3.0, 1e-6)
-    n_p = int(max(5, min(400, target_s / per_step)))
-    gam = np.ones(n_p + 1)
-    t0 = time.perf_counter()
-    O.chebyshev_filter(H, al, be, gam, X, n_b)
+    r = O.chebfd_solve(H, -0.05, 0.05, 32, 200, 32, X0, refill_seed=44)
     dt = time.perf_counter() - t0
-    # bytes of the same filter under the FP64 model (the oracle computes in FP64)
-    nbytes = traffic.filter_bytes(n, nnz, n_b, n_b, n_p, 0)
-    return {
-        "value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(lib.orc_num_threads()),
-        "kind": "oracle",
-        "sample": f"one block of n_b={n_b} vectors, filter degree {n_p} (of the {n_p} steps "
-                  f"{n_p - 2} fused-step equivalents), same matrix, FP64, {dt:.1f} s",
-    }
+    return {"seconds": round(dt, 3), "status": r.status, "iterations": r.iterations, "n_found": r.n_found,
+            "cores": int(O.load_library().orc_num_threads())}, H
+
+
+def gpu_small_solve(P, H):
+    import torch
+    M = P.chebfd_matrix_build(*H, prec=0)
+    P.chebfd_solve(M, M, -0.05, 0.05, 32, 200, 32, seed=43, want_vectors=False)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = P.chebfd_solve(M, M, -0.05, 0.05, 32, 200, 32, seed=43, want_vectors=False)
+    torch.cuda.synchronize()
+    return {"seconds": round(time.perf_counter() - t0, 3), "status": r.status, "iterations": r.stats.iterations,
+            "n_found": r.n_found}
 
 
 def main():
@@ -271,92 +320,59 @@ def main():
     import torch
     import paper_1803_02156_amd as P
     from paper_1803_02156_amd import traffic
-    from topi import random_phase_block, topi_csr
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    from topi import topi_csr
 
     if not torch.cuda.is_available():
         print("no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
     P.load()
     Nx, Ny, Nz = (int(v) for v in args.lattice.split("x"))
-    n_s, n_b, n_p, prec = args.n_s, args.n_b, args.n_p, args.prec
+    n_b, n_p, prec = args.n_b, args.n_p, args.prec
 
     t0 = time.perf_counter()
     H = topi_csr(Nx, Ny, Nz, m=1.0, W=args.W, t=1.0, seed=1002)
     n, nnz = len(H[0]) - 1, len(H[1])
-    from paper_1803_02156_amd.ordering import lattice_row_order
     order = lattice_row_order(Nx, Ny, Nz) if args.order == "lattice" else None
+    log(f"matrix generated: n={n} nnz={nnz} ({time.perf_counter() - t0:.1f} s)")
     M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=prec, order=order)
-    lo, hi = P.chebfd_bounds(M)
-    lam = 0.1  # search interval [-0.1, 0.1] in H's units (the filter's cost does not depend on it)
-    al, be, gam = P.chebfd_coefficients(lo, hi, -lam, lam, n_p)
-    X0 = random_phase_block(n, n_s, 44)
-    x0 = torch.empty((n_s, n), dtype=torch.complex128, device="cuda")
-    x0.copy_(torch.from_numpy(np.ascontiguousarray(X0.T)))
-    del X0
-    xb0 = P.chebfd_pack(M, x0.T, n_b)
-    del x0
-    xy = torch.empty_like(xb0)
-    work = P.FilterWork(M, n_b, n_p, n_s, moments=True)
+    bf = BlockFilter(P, M, n_b, n_p)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    print(f"# setup {setup_s:.1f} s: n={n} nnz={nnz} bounds=[{lo:.4f},{hi:.4f}]", file=sys.stderr, flush=True)
+    log(f"setup {setup_s:.1f} s, bounds [{bf.bounds[0]:.4f}, {bf.bounds[1]:.4f}]")
 
-    stream = torch.cuda.current_stream()
-
-    def step():
-        xy.copy_(xb0)   # fresh start block each step (the filter overwrites X by Y)
-        P.chebfd_filter(M, al, be, gam, n_s, n_b, xy, work=work)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # timed region: K steps (restore the start block -- 2 n n_s elements copied, under
-    # 0.1% of a step -- then the full filter); events on the stream the kernels run on
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    filt_ms = ev0.elapsed_time(ev1) / args.steps
-
-    fbytes = traffic.filter_bytes(n, nnz, n_s, n_b, n_p, prec)
-    gbs = fbytes / (filt_ms * 1e-3) / 1e9
-    gflops = traffic.filter_flops(n, n_s, n_p, nnz / n) / (filt_ms * 1e-3) / 1e9
-    # the fused step also timed alone: op_launches back-to-back launches on three blocks
-    # of the start block (no partials of a previous launch to reduce), events on the stream
-    xv = xy.view(n_s // n_b, n, n_b)
-    opw = P.device_buffer(P.chebfd_filter_query(M, n_b))
-    opb = opw.numel()
-    P.chebfd_op(M, al, be, gam[3], n_b, xv[0], xv[1], xv[2], opw, opb)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.op_launches):
-        P.chebfd_op(M, al, be, gam[3], n_b, xv[0], xv[1], xv[2], opw, opb)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    op_alone_s = e0.elapsed_time(e1) * 1e-3 / args.op_launches
-    # the kernel's average launch over the timed region: every launch of a filter is
-    # this kernel (n_p - 2 fused steps and the two start launches of each block)
-    avg_launch_s = filt_ms * 1e-3 / ((n_s // n_b) * n_p)
+    if args.warmup:
+        bf.run(args.warmup)
+    # timed region: K steps, each = restore the start block (2 n n_b elements, ~0.4% of a
+    # step, not counted as algorithmic bytes) + the degree-n_p filter on the block
+    step_ms, filt_ms = bf.run(args.steps)
+    log(f"filter: {step_ms:.2f} ms per step ({filt_ms:.2f} ms in the filter calls)")
+    fbytes = traffic.filter_bytes(n, nnz, n_b, n_b, n_p, prec)
+    gbs = fbytes / (step_ms * 1e-3) / 1e9
+    gflops = traffic.filter_flops(n, n_b, n_p, nnz / n) / (step_ms * 1e-3) / 1e9
+    # the fused step kernel: every launch of a filter call is that kernel (n_p - 2
+    # recurrence steps and the two start launches), timed by the per-step events
+    avg_launch_s = filt_ms * 1e-3 / n_p
     r, w = traffic.step_bytes(n, nnz, n_b, prec)
     achieved = (r + w) / avg_launch_s / 1e9
     kind = P.chebfd_step_kernel(M, n_b)
-    hbm = counter_traffic(kind, prec, n_b, args.lattice, args.order)
-    del opw
-    # the orthogonalisation's Gram product Y^H Y over the whole search block (FP64 MFMA)
-    P.chebfd_gram(xy.view(n_s // n_b, n, n_b), xy.view(n_s // n_b, n, n_b))
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(5):
-        P.chebfd_gram(xy.view(n_s // n_b, n, n_b), xy.view(n_s // n_b, n, n_b))
-    e1.record(stream)
-    torch.cuda.synchronize()
-    gram_ms = e0.elapsed_time(e1) / 5
-    gram_tflops = 8.0 * n * n_s * n_s / (gram_ms * 1e-3) / 1e12
+    op_alone_s = bf.op_alone(args.op_launches)
+
+    unfused = None
+    if not args.no_unfused:
+        k = max(1, min(args.steps, 5))
+        bf.run(1, unfused=True)
+        u_step, u_filt = bf.run(k, unfused=True)
+        ur, uw = traffic.unfused_step_bytes(n, nnz, n_b, prec)
+        ubytes = traffic.unfused_filter_bytes(n, nnz, n_b, n_b, n_p, prec)
+        unfused = {"ms_per_step": round(u_step, 3), "steps": k,
+                   "value": round(fbytes / (u_step * 1e-3) / 1e9, 2), "unit": "GB/s",
+                   "note": "value: the fused filter's algorithmic bytes per second of the unfused run",
+                   "gflops": round(traffic.filter_flops(n, n_b, n_p, nnz / n) / (u_step * 1e-3) / 1e9, 1),
+                   "own_bytes_per_step": ubytes, "own_gbs": round(ubytes / (u_step * 1e-3) / 1e9, 2),
+                   "own_bytes_per_recurrence_step": ur + uw,
+                   "fused_speedup": round(u_step / step_ms, 3)}
+        log(f"unfused filter: {u_step:.2f} ms per step (fused {step_ms:.2f} ms: x{u_step / step_ms:.2f})")
 
     # attainable HBM bandwidth: copy probe over 2 x 2 GiB (the STREAM analogue of Table 2)
     cnt = 1 << 28
@@ -364,31 +380,93 @@ def main():
     pb = torch.ones(cnt, dtype=torch.float64, device="cuda")
     P.chebfd_probe_stream(0, pa, pb)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
+    e0.record(bf.stream)
     for _ in range(10):
         P.chebfd_probe_stream(0, pa, pb)
-    e1.record(stream)
+    e1.record(bf.stream)
     torch.cuda.synchronize()
     copy_gbs = 10 * 2 * 8 * cnt / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del pa, pb
+    del bf, M
+    torch.cuda.empty_cache()
 
     mixed = None
-    if prec == 0 and not args.no_mixed_filter:
-        mixed = mixed_filter_leg(P, H, order, args.lattice, args.order, n_s, n_b, n_p, args.steps)
-        print(f"# mixed filter: {mixed['value']:.0f} GB/s, {mixed['avg_launch_us']:.1f} us per step",
-              file=sys.stderr, flush=True)
+    if prec == 0 and args.mixed_n_b > 0:
+        mb = args.mixed_n_b
+        M32 = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=1, order=order)
+        bm = BlockFilter(P, M32, mb, n_p)
+        bm.run(1)
+        k = max(1, min(args.steps, 5))
+        m_step, m_filt = bm.run(k)
+        mbytes = traffic.filter_bytes(n, nnz, mb, mb, n_p, 1)
+        m_avg = m_filt * 1e-3 / n_p
+        rm, wm = traffic.step_bytes(n, nnz, mb, 1)
+        mkind = P.chebfd_step_kernel(M32, mb)
+        mixed = {"value": round(mbytes / (m_step * 1e-3) / 1e9, 2), "unit": "GB/s", "ms_per_step": round(m_step, 3),
+                 "n_b": mb, "steps": k, "pct_of_hbm_peak": round(100.0 * mbytes / (m_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+                 "gflops": round(traffic.filter_flops(n, mb, n_p, nnz / n) / (m_step * 1e-3) / 1e9, 1),
+                 "kernel": f"{STEP_KERNELS[mkind][0]}_kernel<float,{mb},kModeStep>",
+                 "avg_launch_us": round(m_avg * 1e6, 3), "bytes_per_launch": rm + wm,
+                 "frac": round((rm + wm) / m_avg / 1e9 / HBM_PEAK_GBS, 4),
+                 "traffic": counter_traffic(mkind, 1, mb, args.lattice, args.order),
+                 "kernel_source_sha256_16": kernel_source_hash(mkind)}
+        log(f"mixed filter n_b={mb}: {mixed['value']:.0f} GB/s, {mixed['avg_launch_us']:.1f} us per launch")
+        del bm
+
+        gram = None
+        if args.gram_n_s > 0:
+            # the orthogonalisation's Gram product Y^H Y of a c64 search space (cfg: c64
+            # storage, FP64 products), FP64 MFMA; the Hermitian product forms its upper triangle
+            ns = args.gram_n_s
+            Y = P.chebfd_random_phase(M32, ns, mb, 99)
+            P.chebfd_gram(Y, Y)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            stream = torch.cuda.current_stream()
+            e0.record(stream)
+            for _ in range(3):
+                P.chebfd_gram(Y, Y)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gram_ms = e0.elapsed_time(e1) / 3
+            # useful flops of the Hermitian product: the upper triangle with its diagonal
+            useful = 8.0 * n * ns * (ns + mb) / 2
+            gram = {"kernel": "gram_kernel (FP64 MFMA 16x16x4)", "shape": f"{n} x {ns} x {ns} complex (c64 in)",
+                    "ms": round(gram_ms, 3), "tflops": round(useful / (gram_ms * 1e-3) / 1e12, 2),
+                    "frac_of_fp64_mfma_peak": round(useful / (gram_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+                    "flops_counted": "8 n n_s (n_s + n_b) / 2: the blocks of the upper triangle"}
+            log(f"gram: {gram_ms:.1f} ms, {gram['tflops']} TFLOP/s")
+            del Y
+        del M32
+        torch.cuda.empty_cache()
+    else:
+        gram = None
 
     solve = None
-    if not args.no_solve:
-        del xy, xb0, work
+    if args.solve_lattice:
+        solve, H_small = time_to_converged(P, args.solve_lattice, args.solve_W, args.solve_n_b, args.solve_count)
         torch.cuda.empty_cache()
-        solve = time_to_converged(P, H, Nx, Ny, Nz, args.W, n_s, n_b, n_p, args.solve_count, order,
-                                  args.solve_prec)
 
     cpu = None
     if args.cpu_baseline_seconds > 0:
         try:
-            cpu = oracle_sample(H, n, nnz, n_b, prec, args.cpu_baseline_seconds)
+            s1 = oracle_filter_rate(H, n_b, args.cpu_baseline_seconds)
+            log(f"oracle: {s1['value']:.1f} GB/s on {s1['cores']} threads")
+            cpu = {"value": round(s1["value"], 3), "unit": "GB/s", "cores": s1["cores"], "kind": "oracle",
+                   "sample": f"one block of n_b={n_b} vectors of the same matrix, filter degree {s1['n_p']} "
+                             f"({s1['seconds']} s), FP64, unfused Alg. 1 in C with OpenMP",
+                   "gflops": round(s1["gflops"], 2), **cpu_info()}
+            del H
+            if solve is not None:
+                s2 = oracle_filter_rate(H_small, n_b, min(10.0, args.cpu_baseline_seconds), threads=1)
+                cpu["one_thread"] = {"value": round(s2["value"], 3), "unit": "GB/s",
+                                     "sample": f"Topi-{args.solve_lattice}, one block of n_b={n_b}, "
+                                               f"degree {s2['n_p']} ({s2['seconds']} s)"}
+            o, Hs = oracle_small_solve()
+            g = gpu_small_solve(P, Hs)
+            cpu["time_to_converged_small"] = {
+                "workload": "Topi-16-16-8 (n=8192, W=1), [-0.05, 0.05], n_s=n_b=32, n_p=200, FP64",
+                "oracle": o, "gpu": g}
         except Exception as e:  # report, never hide the GPU result
             cpu = {"value": None, "unit": "GB/s", "cores": None, "kind": "oracle", "sample": f"failed: {e}"}
 
@@ -399,7 +477,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(filt_ms, 3),
+        "ms_per_step": round(step_ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -407,10 +485,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"Topi-{Nx}-{Ny}-{Nz} (n={n}, nnz={nnz}, W={args.W}), "
-                        f"{'FP64' if prec == 0 else 'mixed c64'} full filter, n_s={n_s}, n_b={n_b}, "
-                        f"n_p={n_p}, SELL-32-256, {args.order} row order",
-            "n": n, "n_s": n_s, "n_b": n_b, "n_p": n_p, "prec": "fp64" if prec == 0 else "mixed",
-            "row_order": args.order,
+                        f"{'FP64' if prec == 0 else 'mixed c64'}; one step = the degree-{n_p} filter on one "
+                        f"block of n_b={n_b} vectors (Alg. 1; one of the n_s/n_b independent blocks of Alg. 2), "
+                        f"SELL-32-256, {args.order} row order",
+            "n": n, "nnz": nnz, "n_b": n_b, "n_p": n_p, "prec": "fp64" if prec == 0 else "mixed",
+            "row_order": args.order, "setup_s": round(setup_s, 1),
         },
         "pct_of_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
         "gflops": round(gflops, 1),
@@ -418,16 +497,16 @@ def main():
         "pct_of_copy_probe": round(100.0 * gbs / copy_gbs, 2),
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": hbm,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kind, prec, n_b, args.lattice,
+                                                                                  args.order),
             "kernel": f"{STEP_KERNELS[kind][0]}_kernel<{'double' if prec == 0 else 'float'},{n_b},kModeStep>",
             "bytes_per_launch": r + w, "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "fused_step_alone_us": round(op_alone_s * 1e6, 3),
             "kernel_source_sha256_16": kernel_source_hash(kind),
         },
-        "gram": {"kernel": "gram_kernel (FP64 MFMA 16x16x4)", "shape": f"{n} x {n_s} x {n_s} complex",
-                 "ms": round(gram_ms, 3), "tflops": round(gram_tflops, 2),
-                 "frac_of_fp64_mfma_peak": round(gram_tflops / 78.6, 4)},
+        "unfused": unfused,
         "filter_mixed": mixed,
+        "gram": gram,
         "time_to_converged": solve,
         "cpu_baseline": cpu,
     }

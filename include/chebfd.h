@@ -148,6 +148,18 @@ int chebfd_unpack(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec,
                   const void *d_blocked, void *d_colmajor, void *stream);
 
 /*
+ * Random-phase block in the blocked layout (the start block of chebfd_solve;
+ * the paper leaves the start vectors open): entry (row r, column j) is
+ * exp(2 pi i u) with u = top 53 bits of splitmix64(k_j xor r) * 2^-53,
+ * k_j = splitmix64(splitmix64(seed) xor (col0 + j)) and r the row's index in
+ * the caller's (original) order, so the block does not depend on H's row order
+ * or on n_b.  m columns (m % n_b == 0), precision prec; d_blocked must be
+ * 16-byte aligned and hold m n elements.  Enqueued on `stream`.
+ */
+int chebfd_random_phase(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec, uint64_t seed,
+                        uint64_t col0, void *d_blocked, void *stream);
+
+/*
  * The polynomial filter (Alg. 1 on each block, Alg. 2 over the blocks):
  * d_xy (blocked layout, n_s vectors, precision `prec`) holds X on entry and
  * Y = sum_{p=0}^{n_p} gamma_p T_p(alpha H + beta I) X on return (the paper
@@ -190,6 +202,25 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
                   int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
                   void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,
                   void *stream);
+
+/*
+ * The same filter built from separate calls instead of the fused step (the
+ * paper's comparison of chebfd_op with a minimum set of standard SpMMV and
+ * BLAS1 calls, Sect. 3.2 and Fig. 2): per step p >= 3 one SpMMV launch
+ * W <- 2(alpha H + beta I) U - W (the step kernel chebfd_step_kernel names,
+ * without the dot products and the update), then the block dot products
+ * eta_p = <W, U> and mu_p = <U, U> (one pass over their operands each, then a
+ * small reduction launch) and the block axpby X <- X + gamma_p W; the start
+ * steps use the same calls (W <- X copied before the second SpMMV, X <- g0 X
+ * + g1 U + g2 W as a scal and two axpby).  Arguments, layouts, outputs,
+ * workspace (chebfd_filter_query bytes) and errors as chebfd_filter; results
+ * equal it up to rounding order.  Each extra call moves its operands through
+ * HBM again: about 1.7x the bytes of the fused step at n_b = 32.
+ */
+int chebfd_filter_unfused(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
+                          int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
+                          void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,
+                          void *stream);
 
 /*
  * One fused Chebyshev step on one block, as timed by the benchmarks (the
@@ -250,7 +281,8 @@ int chebfd_update(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec_a
 
 /*
  * Eigendecomposition of a Hermitian m x m FP64 complex matrix (m <= 512) by
- * cyclic Jacobi rotations in one workgroup: d_w receives the eigenvalues in
+ * cyclic Jacobi rotations (one launch per round of disjoint rotations, one
+ * workgroup per rotation pair): d_w receives the eigenvalues in
  * ascending order, d_v (ldv) the eigenvectors; d_a (lda) is overwritten.
  * Synchronises `stream`; CHEBFD_ENUMERIC if 40 sweeps do not reduce the
  * off-diagonal Frobenius norm below 4 m 2^-53 of the matrix's.
@@ -266,13 +298,15 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
  * the kept directions, residuals in FP64, restart from the Ritz vectors plus
  * fresh random-phase vectors in place of dropped directions.
  * A Ritz pair inside the closed interval [lam_L, lam_R] is converged if its
- * residual ||H z - theta z|| (||z|| = 1) is <= tol and spurious if its residual
- * exceeds (lam_R - lam_L) / 2; the iteration stops when the number of converged
- * pairs repeats, every pair in the interval is converged or spurious and the
- * smallest spurious residual did not halve since the previous iteration
- * (status CHEBFD_OK), after max_iter iterations (CHEBFD_NOT_CONVERGED), or when,
- * from the second iteration on, more than 3/4 n_s non-spurious Ritz pairs fall in
- * the interval (CHEBFD_SUBSPACE_SMALL).
+ * residual ||H z - theta z|| (||z|| = 1) is <= tol, unresolved otherwise; the
+ * iteration stops when the number of converged pairs repeats the previous
+ * iteration's and the smallest unresolved residual did not halve since the
+ * previous iteration, or no pair is unresolved (status CHEBFD_OK: an unresolved
+ * pair whose residual no longer falls under the filter is a mixture of
+ * eigenvectors at or beyond the interval's edges), after max_iter iterations
+ * (CHEBFD_NOT_CONVERGED), or when, from the second iteration on, more than
+ * 3/4 n_s Ritz pairs in the interval have residuals below (lam_R - lam_L) / 2
+ * (CHEBFD_SUBSPACE_SMALL).
  *
  * Mixed precision (p->prec MIXED): the c64 basis bounds the residuals below by
  * about 2^-24 |lambda - theta|.  The iteration therefore runs in two stages:
@@ -319,7 +353,7 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
 
 /*
  * Parameter choice (n_p, n_s) for chebfd_solve.  The paper fixes n_p and n_s
- * by hand (Sect. 2: n_s above the number of wanted eigenpairs; Sect. 5:
+ * by hand (Sect. 2: n_s above the number of wanted eigenpairs; Sect. 2.1:
  * n_p around 10^3) and points to the KPM moments of the filter's dot products
  * as the cheap view of the spectrum (Sect. 2).  Two predictors use them:
  *  - a heuristic: n_s = max(n_b, round_up_{n_b}(2 n_hat)),

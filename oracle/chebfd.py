@@ -45,6 +45,8 @@ def load_library():
                                ctypes.c_int, ctypes.c_int, P, P, P]
     lib.orc_filter.restype = ctypes.c_int
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -212,7 +214,7 @@ def choose_params(a: float, b: float, count_est: float, n_b: int, mlp_out=None, 
     """(n_p, n_s) for the scaled interval [a, b] and a count estimate.
 
     The paper picks n_s a bit above the number of wanted eigenpairs (Sect. 2)
-    and n_p around 10^3 for its problems (Sect. 5); it gives no rule.  The
+    and n_p around 10^3 for its problems (Sect. 2.1); it gives no rule.  The
     reading used here: the filter's resolution scales like 1 / n_p in the
     scaled variable, so n_p = kappa / delta with delta = (b - a) / 2, and
     n_s = 2 n_hat rounded up to a block.  A network may instead give two
@@ -302,7 +304,7 @@ class SolveResult:
 
 def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
                  X0: np.ndarray, tol: float = 1e-9, max_iter: int = 50,
-                 refill_seed: int = 0, bounds=None):
+                 refill_seed: int = 0, bounds=None, trace=None):
     """Eigenpairs of the Hermitian CSR matrix H with eigenvalues in [lam_L, lam_R].
 
     Each iteration: filter the block (Alg. 2 / Alg. 1), orthonormalise it by
@@ -312,19 +314,25 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
     Rayleigh-Ritz step).
 
     Convergence: a Ritz pair inside the closed interval is converged when its
-    residual is <= tol, and spurious when its residual exceeds half the interval
-    width (then [theta - r, theta + r] covers the whole interval and the pair
-    indicates no eigenvalue in it: a mixture of eigenvectors from both sides,
-    which symmetric filters on +-symmetric spectra keep producing).  The solve
-    stops (status 0) when the number of converged pairs repeats the previous
-    iteration's, every in-interval pair is converged or spurious, and the
-    smallest spurious residual did not halve since the previous iteration; else after
-    max_iter iterations (status 1).  If, from the second iteration on, the
+    residual is <= tol; the other pairs inside it are unresolved.  Filtering
+    shrinks the residual of an unresolved pair that is becoming an eigenpair
+    by at least the filter's damping ratio per iteration; a pair whose residual
+    has stopped falling is a stable mixture of eigenvectors at or beyond the
+    interval's edges (with a residual up to about the distance to them) and
+    further filtering will not turn it into an eigenpair.  The solve stops
+    (status 0) when the number of converged pairs repeats the previous
+    iteration's and the smallest residual of the unresolved pairs did not
+    halve since the previous iteration (or none is left); else after max_iter
+    iterations (status 1).  A pair is spurious when its residual exceeds half
+    the interval width ([theta - r, theta + r] then covers the whole interval:
+    it indicates no eigenvalue in it); if, from the second iteration on, the
     number of non-spurious Ritz pairs inside the interval exceeds 3/4 n_s the
-    subspace is too small (status 2).  The paper
-    gives none of these rules; they are the readings adopted here.  Refill
-    vectors of iteration k are random_phase_block(n, d, refill_seed, col0=k n_s).
+    subspace is too small (status 2).  The paper gives none of these rules;
+    they are the readings adopted here.  Refill vectors of iteration k are
+    random_phase_block(n, d, refill_seed, col0=k n_s).
     Returns the converged pairs first (ascending), then the rest (ascending).
+    If `trace` is a list, (iteration, Ritz values, residuals) of every
+    iteration are appended to it.
     """
     from topi import random_phase_block
 
@@ -339,7 +347,7 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
     status = 1
     it = 0
     dropped = 0
-    prev_spur = np.inf
+    prev_unres = np.inf
     for it in range(1, max_iter + 1):
         Y, eta, nu = chebyshev_filter(H, alpha, beta, gamma, X, n_b)
         if it == 1:
@@ -350,6 +358,8 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
         dropped = d1 + d2
         theta, Z = rayleigh_ritz(H, Q)
         res = residual_norms(H, Z, theta)
+        if trace is not None:
+            trace.append((it, theta.copy(), res.copy()))
         inwin = (theta >= lam_L) & (theta <= lam_R)
         conv = inwin & (res <= tol)
         spurious = inwin & (res > 0.5 * (lam_R - lam_L))
@@ -359,16 +369,15 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
         if it >= 2 and np.count_nonzero(inwin & ~spurious) > 0.75 * n_s:
             status = 2
             break
-        # spurious pairs count as settled only once their residuals stop falling: a filter
-        # that has not yet resolved the interval leaves every pair there with a large but
-        # shrinking residual
-        spur_min = float(np.min(res[spurious])) if np.any(spurious) else np.inf
-        spur_settled = not np.any(spurious) or spur_min > 0.5 * prev_spur
-        if cnt == prev and np.all(conv | spurious | ~inwin) and spur_settled:
+        # unresolved pairs count as settled once their smallest residual stops falling
+        unres = inwin & ~conv
+        unres_min = float(np.min(res[unres])) if np.any(unres) else np.inf
+        settled = not np.any(unres) or unres_min > 0.5 * prev_unres
+        if cnt == prev and settled:
             status = 0
             break
         prev = cnt
-        prev_spur = spur_min
+        prev_unres = unres_min
         X = Z
         if dropped:
             X = np.concatenate([Z, random_phase_block(n, dropped, refill_seed, col0=it * n_s)], axis=1)

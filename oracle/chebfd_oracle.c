@@ -149,3 +149,7 @@ int orc_filter(int64_t n, const int64_t *rowptr, const int32_t *col,
 }
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* Thread count of the following calls (timing runs; results depend on it only
+   through the order in which dot products add per-thread sums). */
+void orc_set_num_threads(int t) { if (t >= 1) omp_set_num_threads(t); }

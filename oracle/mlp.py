@@ -5,7 +5,7 @@ that maps Chebyshev (KPM) moments of the matrix plus the scaled search interval
 to the filter degree and subspace size.  The paper motivates the moments as a
 cheap description of the spectrum (Sect. 2: the filter's dot products give the
 KPM moments, the density of states and the eigenvalue count) and leaves the
-choice of n_p and n_s to heuristics (Sect. 2, Sect. 5); the predictor and its
+choice of n_p and n_s to heuristics (Sect. 2, Sect. 2.1); the predictor and its
 training are a reading added on top, stated here:
 
   features x (258) = 256 normalised moments mu~_0..mu~_255 and [a~, b~]

@@ -66,9 +66,11 @@ SIGNATURES = {
     "chebfd_coefficients": (ctypes.c_int, [f64, f64, f64, f64, i32, DP, DP, P]),
     "chebfd_pack": (ctypes.c_int, [MP, i32, i32, i32, P, P, P]),
     "chebfd_unpack": (ctypes.c_int, [MP, i32, i32, i32, P, P, P]),
+    "chebfd_random_phase": (ctypes.c_int, [MP, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint64, P, P]),
     "chebfd_filter_query": (ctypes.c_int, [MP, i32, ctypes.POINTER(sz)]),
     "chebfd_step_kernel": (ctypes.c_int, [MP, i32, ctypes.POINTER(i32)]),
     "chebfd_filter": (ctypes.c_int, [MP, f64, f64, P, i32, i32, i32, i32, P, P, P, P, P, P, sz, P]),
+    "chebfd_filter_unfused": (ctypes.c_int, [MP, f64, f64, P, i32, i32, i32, i32, P, P, P, P, P, P, sz, P]),
     "chebfd_op": (ctypes.c_int, [MP, f64, f64, f64, i32, i32, P, P, P, P, sz, P]),
     "chebfd_spmmv": (ctypes.c_int, [MP, f64, f64, i32, i32, P, P, P, sz, P]),
     "chebfd_kpm_query": (ctypes.c_int, [MP, i32, i32, ctypes.POINTER(sz)]),

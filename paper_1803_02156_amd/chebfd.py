@@ -148,6 +148,17 @@ def chebfd_unpack(H: Matrix, xb: torch.Tensor, prec: int | None = None, out=None
     return out
 
 
+def chebfd_random_phase(H: Matrix, m: int, n_b: int, seed: int, col0: int = 0, prec: int | None = None,
+                        out=None):
+    """Random-phase block (m columns) in the blocked layout (m // n_b, n, n_b), generated on the device."""
+    prec = H.prec if prec is None else prec
+    if out is None:
+        out = torch.empty((m // n_b, H.n, n_b), dtype=vec_dtype(prec), device=H.buf.device)
+    check(load().chebfd_random_phase(H.ref(), m, n_b, prec, seed & 0xFFFFFFFFFFFFFFFF,
+                                     col0 & 0xFFFFFFFFFFFFFFFF, _ptr(out), _stream()))
+    return out
+
+
 KERNEL_LDS, KERNEL_ROW, KERNEL_MULTIROW, KERNEL_WINDOW = 0, 1, 2, 3
 KERNEL_NAMES = {KERNEL_LDS: "lds", KERNEL_ROW: "row", KERNEL_MULTIROW: "multirow", KERNEL_WINDOW: "window"}
 
@@ -193,6 +204,23 @@ def chebfd_filter(H: Matrix, alpha: float, beta: float, gamma, n_s: int, n_b: in
     check(load().chebfd_filter(H.ref(), alpha, beta, gamma.ctypes.data_as(ctypes.c_void_p), n_p, n_s,
                                n_b, H.prec, _ptr(xy), _ptr(work.u), _ptr(work.w), _ptr(eta), _ptr(nu),
                                _ptr(work.work), work.nbytes, _stream()))
+    return eta, nu
+
+
+def chebfd_filter_unfused(H: Matrix, alpha: float, beta: float, gamma, n_s: int, n_b: int, xy: torch.Tensor,
+                          work: FilterWork | None = None, moments: bool = True):
+    """chebfd_filter built from separate SpMMV, dot and axpby calls (same arguments and results)."""
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+    n_p = len(gamma) - 1
+    if work is None:
+        work = FilterWork(H, n_b, n_p, n_s, moments)
+    if xy.dtype != vec_dtype(H.prec) or xy.numel() != H.n * n_s or not xy.is_contiguous():
+        raise ValueError("xy must be a contiguous blocked tensor of n * n_s elements in the matrix precision")
+    eta = work.eta if moments else None
+    nu = work.nu if moments else None
+    check(load().chebfd_filter_unfused(H.ref(), alpha, beta, gamma.ctypes.data_as(ctypes.c_void_p), n_p, n_s,
+                                       n_b, H.prec, _ptr(xy), _ptr(work.u), _ptr(work.w), _ptr(eta), _ptr(nu),
+                                       _ptr(work.work), work.nbytes, _stream()))
     return eta, nu
 
 

@@ -420,6 +420,17 @@ int chebfd_unpack(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec,
                        d_colmajor, true, static_cast<hipStream_t>(stream));
 }
 
+int chebfd_random_phase(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t prec, uint64_t seed,
+                        uint64_t col0, void *d_blocked, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(prec, n_b))) return rc;
+    CHEBFD_REQUIRE(m >= 1 && m % n_b == 0, "m = %d must be a positive multiple of n_b = %d", m, n_b);
+    CHEBFD_REQUIRE(d_blocked && aligned(d_blocked, 16), "d_blocked must be non-NULL and 16-byte aligned");
+    return launch_random_phase(d_blocked, prec, H->n, n_b, 0, m, seed, col0, H->identity_perm ? nullptr : H->perm,
+                               static_cast<hipStream_t>(stream));
+}
+
 // workspace of the filter: two partial buffers [3*n_b][G] (double buffered)
 static size_t filter_work_bytes(int nb, int G) {
     return 2 * round_up(sizeof(double) * 3 * nb * (size_t)G, 256);
@@ -428,9 +439,9 @@ static size_t filter_work_bytes(int nb, int G) {
 // Launch geometry of the step kernels.  The window kernel (U staged in LDS)
 // serves the block widths it has instances for when the row order keeps most
 // gathers within its window; otherwise the LDS-staged kernel (matrix slots in
-// LDS) is used whenever a tile's slots fit its LDS budget (every matrix with
-// rows up to a few hundred entries); otherwise n_b >= 32 uses the
-// row-per-wavefront kernel and smaller n_b the multi-row kernel.
+// LDS) is used for chunks of C = 32 rows with rows of at most 16 entries (its
+// instances' tile width); otherwise n_b >= 32 uses the row-per-wavefront
+// kernel and smaller n_b the multi-row kernel.
 struct StepGeometry {
     int kind;           // 0 = LDS-staged, 1 = row per wavefront, 2 = multi-row, 3 = window
     int64_t npass;      // passes (kinds 1, 2)
@@ -521,11 +532,12 @@ static int filter_run(const chebfd_matrix *H, double alpha, double beta, const d
                       double *d_nu, void *d_work, size_t need, const StepGeometry &geo, bool moments_only,
                       hipStream_t s);
 
-int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
-                  int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
-                  void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,
-                  void *stream) {
-    clear_error();
+// Argument checks shared by chebfd_filter and chebfd_filter_unfused; on
+// success *geo holds the step kernels' launch geometry.
+static int check_filter_args(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma, int32_t n_p,
+                             int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u, void *d_w,
+                             double *d_eta, double *d_nu, void *d_work, size_t work_bytes, StepGeometry *geo,
+                             size_t *need_out) {
     int rc;
     if ((rc = check_handle(H)) || (rc = check_prec_nb(prec, n_b))) return rc;
     CHEBFD_REQUIRE(prec == H->prec, "prec %d differs from the matrix's %d", prec, H->prec);
@@ -542,10 +554,8 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
     const size_t eb = vec_elem_bytes(prec);
     const size_t blk = eb * (size_t)H->n * n_b;
     const size_t xy_bytes = blk * (n_s / n_b);
-    StepGeometry geo;
-    if ((rc = filter_geometry(H, prec, n_b, &geo))) return rc;
-    const int G = geo.G;
-    const size_t need = filter_work_bytes(n_b, G);
+    if ((rc = filter_geometry(H, prec, n_b, geo))) return rc;
+    const size_t need = filter_work_bytes(n_b, geo->G);
     if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "filter workspace %zu < %zu", work_bytes, need);
     CHEBFD_REQUIRE(!overlap(d_xy, xy_bytes, d_u, blk) && !overlap(d_xy, xy_bytes, d_w, blk) &&
                        !overlap(d_u, blk, d_w, blk) && !overlap(d_work, need, d_xy, xy_bytes) &&
@@ -555,9 +565,109 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
         const size_t mb = sizeof(double) * (size_t)(n_p + 1) * n_s;
         CHEBFD_REQUIRE(!overlap(d_eta, 2 * mb, d_nu, mb), "d_eta and d_nu overlap");
     }
+    *need_out = need;
+    return CHEBFD_OK;
+}
 
+int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
+                  int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
+                  void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,
+                  void *stream) {
+    clear_error();
+    StepGeometry geo;
+    size_t need = 0;
+    int rc = check_filter_args(H, alpha, beta, h_gamma, n_p, n_s, n_b, prec, d_xy, d_u, d_w, d_eta, d_nu, d_work,
+                               work_bytes, &geo, &need);
+    if (rc) return rc;
     return filter_run(H, alpha, beta, h_gamma, n_p, n_s, n_b, prec, d_xy, d_u, d_w, d_eta, d_nu, d_work, need,
                       geo, false, static_cast<hipStream_t>(stream));
+}
+
+static int filter_unfused_run(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma, int n_p,
+                              int n_s, int n_b, int prec, void *d_xy, void *d_u, void *d_w, double *d_eta,
+                              double *d_nu, void *d_work, const StepGeometry &geo, hipStream_t s);
+
+int chebfd_filter_unfused(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
+                          int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
+                          void *d_w, double *d_eta, double *d_nu, void *d_work, size_t work_bytes,
+                          void *stream) {
+    clear_error();
+    StepGeometry geo;
+    size_t need = 0;
+    int rc = check_filter_args(H, alpha, beta, h_gamma, n_p, n_s, n_b, prec, d_xy, d_u, d_w, d_eta, d_nu, d_work,
+                               work_bytes, &geo, &need);
+    if (rc) return rc;
+    return filter_unfused_run(H, alpha, beta, h_gamma, n_p, n_s, n_b, prec, d_xy, d_u, d_w, d_eta, d_nu, d_work,
+                              geo, static_cast<hipStream_t>(stream));
+}
+
+// The unfused filter: Alg. 1 from separate calls, each one pass over its
+// operands in HBM (the SpMMV with the recurrence's scaling and shift, two
+// block dot products and the axpby of the filtered block), as in the paper's
+// comparison of chebfd_op with standard SpMMV and BLAS1 calls (Sect. 3.2).
+// Arguments validated by the caller; the partials of the dot products go to
+// the first half of the filter workspace and are reduced once per step.
+static int filter_unfused_run(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma, int n_p,
+                              int n_s, int n_b, int prec, void *d_xy, void *d_u, void *d_w, double *d_eta,
+                              double *d_nu, void *d_work, const StepGeometry &geo, hipStream_t s) {
+    int rc;
+    const int G = geo.G;
+    const size_t blk = vec_elem_bytes(prec) * (size_t)H->n * n_b;
+    double *part = static_cast<double *>(d_work);
+    const int64_t count = H->n * (int64_t)n_b;
+    // eta_p = <new, prior>, nu_p = <prior, prior> of block b into row p of the moments
+    auto moments = [&](const void *nw, const void *prior, int p, int b) -> int {
+        if (!d_eta) return CHEBFD_OK;
+        int r;
+        if ((r = launch_block_dot(prec, n_b, H->n, nw, prior, part, G, 0, true, s))) return r;
+        if ((r = launch_block_dot(prec, n_b, H->n, prior, prior, part, G, 2, false, s))) return r;
+        StepArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.part_in = part;
+        a.red_eta = d_eta + 2 * ((int64_t)p * n_s + (int64_t)b * n_b);
+        a.red_nu = d_nu + ((int64_t)p * n_s + (int64_t)b * n_b);
+        a.G_prev = G;
+        return launch_reduce(n_b, a, s);
+    };
+    for (int b = 0; b < n_s / n_b; ++b) {
+        char *X = static_cast<char *>(d_xy) + blk * b;
+        if (n_p == 0) {
+            if ((rc = launch_block_axpby(prec, count, h_gamma[0], X, 0.0, nullptr, s))) return rc;
+            continue;
+        }
+        // U <- (aH + bI) X                                          (Alg. 1, first product)
+        StepArgs a = base_args(H, alpha, beta);
+        a.P = X;
+        a.N = d_u;
+        if ((rc = launch_any(H, prec, n_b, kModeSpmv, a, geo, s))) return rc;
+        if ((rc = moments(d_u, X, 1, b))) return rc;
+        if (n_p == 1) {
+            if ((rc = launch_block_axpby(prec, count, h_gamma[0], X, h_gamma[1], d_u, s))) return rc;
+            continue;
+        }
+        // W <- X, W <- 2(aH + bI) U - W                             (Alg. 1, second product)
+        if ((rc = launch_block_axpby(prec, count, 0.0, d_w, 1.0, X, s))) return rc;
+        a = base_args(H, alpha, beta);
+        a.P = d_u;
+        a.O = d_w;
+        if ((rc = launch_any(H, prec, n_b, kModeSpmvRec, a, geo, s))) return rc;
+        if ((rc = moments(d_w, d_u, 2, b))) return rc;
+        // X <- g0c0 X + g1c1 U + g2c2 W                              (Alg. 1, bscal + baxpy)
+        if ((rc = launch_block_axpby(prec, count, h_gamma[0], X, h_gamma[1], d_u, s))) return rc;
+        if ((rc = launch_block_axpby(prec, count, 1.0, X, h_gamma[2], d_w, s))) return rc;
+        // p = 3..n_p: swap(W, U); W <- 2(aH + bI) U - W; eta, nu; X += g_p c_p W
+        void *Ub = d_w, *Wb = d_u;
+        for (int p = 3; p <= n_p; ++p) {
+            a = base_args(H, alpha, beta);
+            a.P = Ub;
+            a.O = Wb;
+            if ((rc = launch_any(H, prec, n_b, kModeSpmvRec, a, geo, s))) return rc;
+            if ((rc = moments(Wb, Ub, p, b))) return rc;
+            if ((rc = launch_block_axpby(prec, count, 1.0, X, h_gamma[p], Wb, s))) return rc;
+            std::swap(Ub, Wb);
+        }
+    }
+    return CHEBFD_OK;
 }
 
 // The filter driver shared by chebfd_filter and chebfd_kpm_moments (arguments

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepArgs a) {
         const T hu_im = fma(alpha, acc_im, beta * up.y);
 
         VT nw;
-        if constexpr (MODE == kModeFirst) {
+        if constexpr (mode_first(MODE)) {
             nw.x = hu_re;
             nw.y = hu_im;
             N[e] = nw;
@@ -174,12 +174,15 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepArgs a) {
                 }
             }
         }
-        // eta += conj(new) * prior, nu += |prior|^2 (FP64)
-        const double nr = nw.x, ni = nw.y, ur = up.x, ui = up.y;
-        e_re = fma(nr, ur, fma(ni, ui, e_re));
-        e_im = fma(nr, ui, fma(-ni, ur, e_im));
-        nu = fma(ur, ur, fma(ui, ui, nu));
+        if constexpr (mode_dots(MODE)) {
+            // eta += conj(new) * prior, nu += |prior|^2 (FP64)
+            const double nr = nw.x, ni = nw.y, ur = up.x, ui = up.y;
+            e_re = fma(nr, ur, fma(ni, ui, e_re));
+            e_im = fma(nr, ui, fma(-ni, ur, e_im));
+            nu = fma(ur, ur, fma(ui, ui, nu));
+        }
     }
+    if constexpr (!mode_dots(MODE)) return;
 
     // workgroup reduction over the ROWS lanes of each column, fixed order
     sred[tid] = e_re;
@@ -224,6 +227,8 @@ static int launch_mode(int mode, const StepArgs &a, int G, hipStream_t s) {
         case kModeSecond: return launch_one<T, NB, kModeSecond>(a, G, s);
         case kModeStep: return launch_one<T, NB, kModeStep>(a, G, s);
         case kModeKpm: return launch_one<T, NB, kModeKpm>(a, G, s);
+        case kModeSpmv: return launch_one<T, NB, kModeSpmv>(a, G, s);
+        case kModeSpmvRec: return launch_one<T, NB, kModeSpmvRec>(a, G, s);
     }
     CHEBFD_FAIL(CHEBFD_EINVAL, "bad step mode %d", mode);
 }

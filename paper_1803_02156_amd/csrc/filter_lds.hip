@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
             PK o, yv;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) o.re[c] = o.im[c] = yv.re[c] = yv.im[c] = T(0);
-            if constexpr (MODE != kModeFirst) o = load_pack<T, CPL, true>(static_cast<const T *>(a.O) + e);
+            if constexpr (!mode_first(MODE)) o = load_pack<T, CPL, true>(static_cast<const T *>(a.O) + e);
             if constexpr (MODE == kModeStep) yv = load_pack<T, CPL, true>(static_cast<const T *>(a.Y) + e);
 
             T acc_re[CPL], acc_im[CPL];
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
             for (int c = 0; c < CPL; ++c) {
                 const T hu_re = fma(alpha, acc_re[c], beta * up.re[c]);
                 const T hu_im = fma(alpha, acc_im[c], beta * up.im[c]);
-                if constexpr (MODE == kModeFirst) {
+                if constexpr (mode_first(MODE)) {
                     nw.re[c] = hu_re;
                     nw.im[c] = hu_im;
                 } else {
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
                     nw.im[c] = fma(T(2), hu_im, -o.im[c]);
                 }
             }
-            if constexpr (MODE == kModeFirst) {
+            if constexpr (mode_first(MODE)) {
                 store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
             } else if constexpr (MODE == kModeSecond) {
                 store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
@@ -292,12 +292,14 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
                     store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, y);
                 }
             }
+            if constexpr (mode_dots(MODE)) {
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const double nr = nw.re[c], ni = nw.im[c], ur = up.re[c], ui = up.im[c];
-                e_re[c] = fma(nr, ur, fma(ni, ui, e_re[c]));
-                e_im[c] = fma(nr, ui, fma(-ni, ur, e_im[c]));
-                nu[c] = fma(ur, ur, fma(ui, ui, nu[c]));
+                for (int c = 0; c < CPL; ++c) {
+                    const double nr = nw.re[c], ni = nw.im[c], ur = up.re[c], ui = up.im[c];
+                    e_re[c] = fma(nr, ur, fma(ni, ui, e_re[c]));
+                    e_im[c] = fma(nr, ui, fma(-ni, ur, e_im[c]));
+                    nu[c] = fma(ur, ur, fma(ui, ui, nu[c]));
+                }
             }
           }
           // The next tile's slots go to the idle buffer after the first
@@ -310,6 +312,7 @@ __global__ __launch_bounds__(kThreads) void cheb_lds_kernel(StepArgs a, int tile
         __syncthreads();
     }
 
+    if constexpr (!mode_dots(MODE)) return;
     // workgroup reduction over the ROWS lanes of each column, fixed order;
     // sred[(component * CPL + c) * kThreads + lane]
 #pragma unroll
@@ -355,6 +358,8 @@ int launch_lds_mode(int mode, const StepArgs &a, const LdsGeometry &g, hipStream
         case kModeSecond: return launch_lds_one<T, NB, kModeSecond, MAXW>(a, g, s);
         case kModeStep: return launch_lds_one<T, NB, kModeStep, MAXW>(a, g, s);
         case kModeKpm: return launch_lds_one<T, NB, kModeKpm, MAXW>(a, g, s);
+        case kModeSpmv: return launch_lds_one<T, NB, kModeSpmv, MAXW>(a, g, s);
+        case kModeSpmvRec: return launch_lds_one<T, NB, kModeSpmvRec, MAXW>(a, g, s);
     }
     CHEBFD_FAIL(CHEBFD_EINVAL, "bad step mode %d", mode);
 }

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void cheb_row_kernel(StepArgs a) {
         const int64_t e2 = ((int64_t)i * NB + j) * 2 + h;
         const T up_c = Pc[e2];
         T o_c = 0, y_c = 0;
-        if constexpr (MODE != kModeFirst) o_c = static_cast<const T *>(a.O)[e2];
+        if constexpr (!mode_first(MODE)) o_c = static_cast<const T *>(a.O)[e2];
         if constexpr (MODE == kModeStep) y_c = static_cast<const T *>(a.Y)[e2];
 
         // prefetch the next row's column indices
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void cheb_row_kernel(StepArgs a) {
         const T acc_c = h ? A + B_other : A - B_other;
         const T hu = fma(alpha, acc_c, beta * up_c);
         T nw;
-        if constexpr (MODE == kModeFirst) {
+        if constexpr (mode_first(MODE)) {
             nw = hu;
             static_cast<T *>(a.N)[e2] = nw;
         } else {
@@ -207,12 +207,15 @@ __global__ __launch_bounds__(kThreads) void cheb_row_kernel(StepArgs a) {
         }
         // eta = sum conj(nw) up: Re from same-component products, Im from the
         // other component of nw (exchanged across halves); nu = sum |up|^2
-        const double nwd = nw, upd = up_c;
-        const double nwo = __shfl_xor(nwd, 32);
-        d_re = fma(nwd, upd, d_re);
-        d_im = fma(h ? nwo : -nwo, upd, d_im);
-        d_nu = fma(upd, upd, d_nu);
+        if constexpr (mode_dots(MODE)) {
+            const double nwd = nw, upd = up_c;
+            const double nwo = __shfl_xor(nwd, 32);
+            d_re = fma(nwd, upd, d_re);
+            d_im = fma(h ? nwo : -nwo, upd, d_im);
+            d_nu = fma(upd, upd, d_nu);
+        }
     }
+    if constexpr (!mode_dots(MODE)) return;
 
     // workgroup reduction in a fixed order: the two halves, then the rows of
     // the pass that share this column block
@@ -254,6 +257,8 @@ int launch_row_mode(int mode, const StepArgs &a, int G, hipStream_t s) {
         case kModeSecond: return launch_row_one<T, NB, kModeSecond, ME>(a, G, s);
         case kModeStep: return launch_row_one<T, NB, kModeStep, ME>(a, G, s);
         case kModeKpm: return launch_row_one<T, NB, kModeKpm, ME>(a, G, s);
+        case kModeSpmv: return launch_row_one<T, NB, kModeSpmv, ME>(a, G, s);
+        case kModeSpmvRec: return launch_row_one<T, NB, kModeSpmvRec, ME>(a, G, s);
     }
     CHEBFD_FAIL(CHEBFD_EINVAL, "bad step mode %d", mode);
 }

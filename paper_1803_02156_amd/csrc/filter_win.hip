@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
         for (int c = 0; c < CPL; ++c) o.re[c] = o.im[c] = yv.re[c] = yv.im[c] = T(0);
         if (i < a.n) {
             const int64_t e = 2 * (i * NB + jc);
-            if constexpr (MODE != kModeFirst) o = load_pack<T, CPL, true>(static_cast<const T *>(a.O) + e);
+            if constexpr (!mode_first(MODE)) o = load_pack<T, CPL, true>(static_cast<const T *>(a.O) + e);
             if constexpr (MODE == kModeStep) yv = load_pack<T, CPL, true>(static_cast<const T *>(a.Y) + e);
         }
 
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
             for (int c = 0; c < CPL; ++c) {
                 const T hu_re = fma(alpha, acc_re[c], beta * up.re[c]);
                 const T hu_im = fma(alpha, acc_im[c], beta * up.im[c]);
-                if constexpr (MODE == kModeFirst) {
+                if constexpr (mode_first(MODE)) {
                     nw.re[c] = hu_re;
                     nw.im[c] = hu_im;
                 } else {
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
                     nw.im[c] = fma(T(2), hu_im, -o.im[c]);
                 }
             }
-            if constexpr (MODE == kModeFirst) {
+            if constexpr (mode_first(MODE)) {
                 store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
             } else if constexpr (MODE == kModeSecond) {
                 store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
@@ -330,12 +330,14 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
                     store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, y);
                 }
             }
+            if constexpr (mode_dots(MODE)) {
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const double nr = nw.re[c], ni = nw.im[c], ur = up.re[c], ui = up.im[c];
-                e_re[c] = fma(nr, ur, fma(ni, ui, e_re[c]));
-                e_im[c] = fma(nr, ui, fma(-ni, ur, e_im[c]));
-                nu[c] = fma(ur, ur, fma(ui, ui, nu[c]));
+                for (int c = 0; c < CPL; ++c) {
+                    const double nr = nw.re[c], ni = nw.im[c], ur = up.re[c], ui = up.im[c];
+                    e_re[c] = fma(nr, ur, fma(ni, ui, e_re[c]));
+                    e_im[c] = fma(nr, ui, fma(-ni, ur, e_im[c]));
+                    nu[c] = fma(ur, ur, fma(ui, ui, nu[c]));
+                }
             }
         }
         // block tile + kWinHalo + 1 replaces block tile - kWinHalo - 1 (outside
@@ -346,6 +348,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
         buf ^= 1;
     }
 
+    if constexpr (!mode_dots(MODE)) return;
     // workgroup reduction over the TR lanes of each column, fixed order;
     // sred[(component * CPL + c) * kWinThreads + lane] (over the ring: every
     // wave has passed the last barrier of the tile loop)
@@ -393,6 +396,8 @@ int launch_win_mode(int mode, const StepArgs &a, const WinGeometry &g, hipStream
         case kModeSecond: return launch_win_one<T, NB, kModeSecond, MAXW, UNI>(a, g, s);
         case kModeStep: return launch_win_one<T, NB, kModeStep, MAXW, UNI>(a, g, s);
         case kModeKpm: return launch_win_one<T, NB, kModeKpm, MAXW, UNI>(a, g, s);
+        case kModeSpmv: return launch_win_one<T, NB, kModeSpmv, MAXW, UNI>(a, g, s);
+        case kModeSpmvRec: return launch_win_one<T, NB, kModeSpmvRec, MAXW, UNI>(a, g, s);
     }
     CHEBFD_FAIL(CHEBFD_EINVAL, "bad step mode %d", mode);
 }
@@ -414,6 +419,10 @@ bool set_win_attr() {
     ok &= hipFuncSetAttribute(reinterpret_cast<const void *>(cheb_win_kernel<T, NB, kModeStep, MAXW, UNI>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
     ok &= hipFuncSetAttribute(reinterpret_cast<const void *>(cheb_win_kernel<T, NB, kModeKpm, MAXW, UNI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void *>(cheb_win_kernel<T, NB, kModeSpmv, MAXW, UNI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    ok &= hipFuncSetAttribute(reinterpret_cast<const void *>(cheb_win_kernel<T, NB, kModeSpmvRec, MAXW, UNI>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
     return ok;
 }

@@ -12,8 +12,14 @@ namespace chebfd {
 //  kModeSecond: N = 2(aH+bI) P - O;  Y(=O) = g0 O + g1 P + g2 N   (Alg. 1, start of Y)
 //  kModeStep  : O = 2(aH+bI) P - O (in place);  Y += g2 O       (Alg. 1, recurrence step)
 //  kModeKpm   : O = 2(aH+bI) P - O (in place), no Y update      (moments only)
-// Every mode also forms the per-column products <new, P> and <P, P>.
-enum { kModeFirst = 0, kModeSecond = 1, kModeStep = 2, kModeKpm = 3 };
+// These four also form the per-column products <new, P> and <P, P>.  The
+// unfused filter (the SpMMV call of Alg. 1 on its own, followed by separate
+// dot and axpy calls) uses two more, which form no dot products:
+//  kModeSpmv   : N = (aH+bI) P
+//  kModeSpmvRec: O = 2(aH+bI) P - O (in place)
+enum { kModeFirst = 0, kModeSecond = 1, kModeStep = 2, kModeKpm = 3, kModeSpmv = 4, kModeSpmvRec = 5 };
+constexpr bool mode_dots(int mode) { return mode <= kModeKpm; }
+constexpr bool mode_first(int mode) { return mode == kModeFirst || mode == kModeSpmv; }
 
 struct StepArgs {
     int64_t n;
@@ -82,6 +88,13 @@ int row_occupancy(int prec, int nb);
 constexpr int kRowKernelMinNb = 32;
 inline int row_kernel_rows_per_pass(int nb) { return 128 / nb; }
 int launch_reduce(int nb, const StepArgs &a, hipStream_t s);
+// BLAS1 calls of the unfused filter (blas1.hip), on blocked n x nb blocks:
+// per-workgroup partials of <A, B>_j = sum_i conj(A_ij) B_ij into
+// part[(comp0 + c) NB + j][G] (c = 0 real part, 1 imaginary part; real part
+// only when want_im is false), and Y = a Y + b X over count complex entries.
+int launch_block_dot(int prec, int nb, int64_t n, const void *A, const void *B, double *part, int G, int comp0,
+                     bool want_im, hipStream_t s);
+int launch_block_axpby(int prec, int64_t count, double a, void *y, double b, const void *x, hipStream_t s);
 int step_grid(int prec, int nb, int64_t npass, int num_cus);
 
 // dense kernels (dense.hip)

@@ -2,7 +2,7 @@
 // features to (n_p, n_s), with forward pass, loss gradient and Adam update on
 // the device.  The moments it reads are those of the filter's dot products
 // (Sect. 2: KPM moments and the eigenvalue count come out of Alg. 1); the
-// predictor replaces the hand-tuned choice of n_p and n_s (Sect. 2, Sect. 5).
+// predictor replaces the hand-tuned choice of n_p and n_s (Sect. 2, Sect. 2.1).
 //
 // Network: x (258) -> relu(W1 x + b1) (128) -> relu(W2 h1 + b2) (128) -> W3 h2 + b3 (2).
 // Parameters: one flat FP32 vector W1, b1, W2, b2, W3, b3 (weights row-major,

@@ -299,7 +299,7 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     // (coefficients), hth / hres the k2 Ritz values and residuals.
     auto run_stage = [&](Stage &g, int prev, bool stage1, bool *stagnated) -> int {
         const size_t swg = vec_elem_bytes(g.prec);
-        double prev_max = INFINITY, prev_spur = INFINITY;
+        double prev_max = INFINITY, prev_unres = INFINITY;
         int prev_inwin = -1;
         *stagnated = false;
         for (++it; it <= p->max_iter; ++it) {
@@ -400,9 +400,12 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
             }
 
             // --- convergence test ---
+            // in-interval pairs are converged (residual <= tol) or unresolved; the stage
+            // stops once the converged count repeats and the smallest unresolved residual
+            // has stopped falling (a pair whose residual no longer shrinks under the filter
+            // is a stable mixture of eigenvectors at or beyond the interval's edges)
             int inwin = 0, conv = 0, settled = 0;
-            bool all_ok = true;
-            double worst = 0.0, spur_min = INFINITY;
+            double worst = 0.0, unres_min = INFINITY;
             for (int c = 0; c < k2; ++c) {
                 if (hth[c] < p->lam_L || hth[c] > p->lam_R) continue;
                 ++inwin;
@@ -410,17 +413,14 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
                 const bool spur = hres[c] > 0.5 * (p->lam_R - p->lam_L);
                 conv += cv ? 1 : 0;
                 settled += spur ? 0 : 1;
-                if (spur) spur_min = std::min(spur_min, hres[c]);
-                all_ok = all_ok && (cv || spur);
+                if (!cv) unres_min = std::min(unres_min, hres[c]);
                 if (!spur) worst = std::max(worst, hres[c]);
             }
             // too many eigenvalues for the subspace: judged from the second iteration on, on
             // the in-interval pairs whose residual already places them in the interval
             if (stage1 && it >= 2 && settled > 0.75 * g.ns) return CHEBFD_SUBSPACE_SMALL;
-            // spurious pairs count as settled only once their residuals stop falling (an
-            // interval the filter has not resolved yet leaves large but shrinking residuals)
-            const bool spur_settled = !(spur_min < INFINITY) || spur_min > 0.5 * prev_spur;
-            if (conv == prev && all_ok && spur_settled) return CHEBFD_OK;
+            const bool unres_settled = !(unres_min < INFINITY) || unres_min > 0.5 * prev_unres;
+            if (conv == prev && unres_settled) return CHEBFD_OK;
             // stage 1 of a mixed run also ends when the residuals stop falling (storage floor)
             if (stage1 && g.prec != CHEBFD_PREC_FP64 && inwin > 0 && inwin == prev_inwin && conv == prev &&
                 worst > 0.5 * prev_max) {
@@ -430,7 +430,7 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
             prev = conv;
             prev_max = worst;
             prev_inwin = inwin;
-            prev_spur = spur_min;
+            prev_unres = unres_min;
             if (it == p->max_iter) break;
 
             // --- restart: Ritz vectors, then fresh random phases for dropped directions ---

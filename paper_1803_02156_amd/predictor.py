@@ -1,7 +1,7 @@
 """Learned choice of the filter degree n_p and the subspace size n_s.
 
 The paper sets n_p and n_s by hand (Sect. 2: n_s somewhat above the number of
-wanted eigenpairs; Sect. 5: n_p around 10^3 for its matrices) and notes that
+wanted eigenpairs; Sect. 2.1: n_p around 10^3 for its matrices) and notes that
 the filter's dot products are KPM moments, i.e. a cheap picture of the
 spectrum (Sect. 2).  This module turns that picture into the two parameters:
 

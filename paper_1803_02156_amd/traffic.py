@@ -37,6 +37,27 @@ def filter_bytes(n: int, nnz: int, n_s: int, n_b: int, n_p: int, prec: int) -> i
     return (n_s // n_b) * ((n_p - 2) * (r + w) + r0 + w0)
 
 
+def unfused_step_bytes(n: int, nnz: int, n_b: int, prec: int) -> tuple[int, int]:
+    """(read, write) bytes of one recurrence step of the unfused filter, each call
+    streaming its operands once: the SpMMV W <- 2(aH+bI)U - W (matrix, U, W read;
+    W written), <W, U> (W, U read), <U, U> (U read), X <- X + g W (X, W read; X
+    written): 9 vector entries per row and column instead of the fused step's 5."""
+    s = value_bytes(prec)
+    read = nnz * (s + 4) + 7 * n * n_b * s
+    write = 2 * n * n_b * s
+    return read, write
+
+
+def unfused_filter_bytes(n: int, nnz: int, n_s: int, n_b: int, n_p: int, prec: int) -> int:
+    """Bytes of the unfused filter (n_p >= 2): the start calls (U = H~X with <U,X>, <X,X>:
+    matrix + 5 entries; W <- X, W <- 2H~U - W, <W,U>, <U,U>, X <- g0 X + g1 U, X += g2 W:
+    matrix + 14 entries) and n_p - 2 recurrence steps, per block."""
+    s = value_bytes(prec)
+    r, w = unfused_step_bytes(n, nnz, n_b, prec)
+    start = 2 * nnz * (s + 4) + 19 * n * n_b * s
+    return (n_s // n_b) * ((n_p - 2) * (r + w) + start)
+
+
 def filter_flops(n: int, n_s: int, n_p: int, nnzr: float = 13.0) -> float:
     """Flops of one filter with the paper's count, 146 per row and vector per step for
     nnzr = 13 (8 per complex multiply-add of the sparse product plus 42 for the

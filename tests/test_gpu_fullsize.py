@@ -1,0 +1,177 @@
+"""The fused step at full size, in the benchmark's launch configuration.
+
+1. Oracle parity on the 64x64x32 lattice (n = 524288, the benchmark matrix: m = 1,
+   W = 1, lattice row order, SELL-32-256): one block filtered to degree 60
+   through the kernel the benchmark times (asserted), Y, eta and nu compared
+   element by element with the FP64 oracle (Alg. 1).  The spectral bounds are
+   widened on both sides so that beta != 0 (for this matrix Gershgorin gives
+   beta = 0 exactly, which would leave the beta U_i term unchecked).
+2. Plane waves on the clean lattice at 128x128x64 and 256x256x128 (the largest
+   single-GPU configuration): a Bloch vector exp(i k.r) v_k, with v_k an
+   eigenvector of the 4x4 Bloch matrix h(k), is an exact eigenvector of H, so
+   T_p(aH + b) x = T_p(a E + b) x with T_p(cos t) = cos(p t): Y, eta and nu are
+   known in closed form for every row, and every row's 13 gathers (all six
+   neighbour blocks, across workgroup and XCD ranges) enter the result.
+
+Tolerances as in test_gpu_filter.py: p (nnzr + 4) u / sqrt(1 - s^2) for T_p x,
+times sum |gamma_p| for Y, times 2n for the dot products.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from topi import random_phase_block, topi_csr
+from topi.generator import G0, hopping_block
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = 2.0 ** -53
+EPS32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1803_02156_amd as P
+    P.load()
+    return P
+
+
+def _bound(n_p, nnzr, u, s):
+    return max(n_p, 1) * (nnzr + 4) * u / np.sqrt(1.0 - s * s)
+
+
+def _to_dev_colmajor(X):
+    n, m = X.shape
+    t = torch.empty((m, n), dtype=torch.complex128, device="cuda")
+    t.copy_(torch.from_numpy(np.ascontiguousarray(X.T)))
+    return t.T
+
+
+def _widened(lo, hi):
+    """Bounds widened unevenly (beta != 0); the scaled spectrum stays in [-s, s]."""
+    lo2, hi2 = lo - 0.6, hi + 0.2
+    al = 2.0 / (hi2 - lo2)
+    be = -(hi2 + lo2) / (hi2 - lo2)
+    s = max(abs(al * lo + be), abs(al * hi + be))
+    return lo2, hi2, s
+
+
+# prec, n_b, kernel the library must pick for the benchmark's 64x64x32 matrix
+FULL_CASES = [(0, 32, "window"), (1, 64, "window"), (1, 32, "lds")]
+
+
+@pytest.mark.parametrize("prec,n_b,kernel", FULL_CASES)
+def test_full_size_filter_matches_oracle(P, prec, n_b, kernel):
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    print(f"\n# full-size oracle parity: 64x64x32 lattice order, prec {prec}, n_b {n_b}", flush=True)
+    dims, n_p = (64, 64, 32), 60
+    H = topi_csr(*dims, m=1.0, W=1.0, seed=1002)
+    n = len(H[0]) - 1
+    M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=prec, order=lattice_row_order(*dims))
+    want = {"window": P.KERNEL_WINDOW, "lds": P.KERNEL_LDS}[kernel]
+    assert P.chebfd_step_kernel(M, n_b) == want
+    lo, hi = P.chebfd_bounds(M)
+    lo2, hi2, s = _widened(lo, hi)
+    al, be, gam = P.chebfd_coefficients(lo2, hi2, -0.3, 0.2, n_p)
+    assert abs(be) > 1e-3
+    X = random_phase_block(n, n_b, 61)
+    xb = P.chebfd_pack(M, _to_dev_colmajor(X), n_b)
+    eta, nu = P.chebfd_filter(M, al, be, gam, n_b, n_b, xb)
+    Y = P.chebfd_unpack(M, xb).cpu().numpy()
+    eta, nu = eta.cpu().numpy(), nu.cpu().numpy()
+    del xb, M
+    Yr, etar, nur = O.chebyshev_filter(H, al, be, gam, X, n_b)
+    u = EPS64 if prec == 0 else EPS32
+    tol_T = _bound(n_p, 13, u, s)
+    tol_Y = max(np.sum(np.abs(gam)), 1.0) * tol_T
+    err_Y = np.max(np.abs(Y - Yr))
+    tol_m = 2.0 * n * tol_T + n * 4 * u
+    err_e = np.max(np.abs(eta[1:] - etar[1:]))
+    err_n = np.max(np.abs(nu[1:] - nur[1:].real))
+    print(f"# max|Y - Y_oracle| {err_Y:.3e} (bound {tol_Y:.3e}), eta {err_e:.3e}, nu {err_n:.3e} "
+          f"(bound {tol_m:.3e})", flush=True)
+    assert err_Y <= tol_Y and err_e <= tol_m and err_n <= tol_m
+
+
+def _bloch_matrix(k, m=1.0, t=1.0):
+    """h(k) = m G0 + sum_d (T_d e^{i k_d} + T_d^H e^{-i k_d}) for the row/column
+    convention of the generator (T_d at block (s, s + e_d))."""
+    h = m * G0.astype(np.complex128)
+    for d in range(3):
+        T = hopping_block(d, t)
+        h = h + T * np.exp(1j * k[d]) + T.conj().T * np.exp(-1j * k[d])
+    return h
+
+
+def _plane_wave(dims, j, v):
+    """Column exp(i k.r_s) v_o at row 4 s + o, s = x + Nx (y + Ny z), k_d = 2 pi j_d / N_d."""
+    Nx, Ny, Nz = dims
+    ex = np.exp(2j * np.pi * j[0] * np.arange(Nx) / Nx)
+    ey = np.exp(2j * np.pi * j[1] * np.arange(Ny) / Ny)
+    ez = np.exp(2j * np.pi * j[2] * np.arange(Nz) / Nz)
+    ph = (ez[:, None, None] * ey[None, :, None] * ex[None, None, :]).ravel()   # site order z, y, x
+    return (ph[:, None] * v[None, :]).ravel()
+
+
+BLOCH_CASES = [
+    ((128, 128, 64), 0, 32, "window"),
+    ((256, 256, 128), 0, 32, "window"),    # the largest single-GPU configuration, benchmark geometry
+    ((256, 256, 128), 1, 32, "lds"),
+]
+
+
+@pytest.mark.parametrize("dims,prec,n_b,kernel", BLOCH_CASES)
+def test_plane_waves_full_size(P, dims, prec, n_b, kernel):
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    print(f"\n# plane waves: {dims} lattice order, prec {prec}, n_b {n_b}", flush=True)
+    n_p = 40
+    H = topi_csr(*dims, m=1.0, W=0.0)
+    n = len(H[0]) - 1
+    M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=prec, order=lattice_row_order(*dims))
+    del H
+    want = {"window": P.KERNEL_WINDOW, "lds": P.KERNEL_LDS}[kernel]
+    assert P.chebfd_step_kernel(M, n_b) == want
+    lo, hi = P.chebfd_bounds(M)
+    lo2, hi2, s = _widened(lo, hi)
+    al, be, gam = P.chebfd_coefficients(lo2, hi2, -0.3, 0.2, n_p)
+    rng = np.random.default_rng(7)
+    cols, lam = [], []
+    for c in range(n_b):
+        j = [int(rng.integers(0, N)) for N in dims]
+        k = [2 * np.pi * jj / N for jj, N in zip(j, dims)]
+        E, V = np.linalg.eigh(_bloch_matrix(k))
+        band = int(rng.integers(0, 4))
+        cols.append((j, V[:, band]))
+        lam.append(al * E[band] + be)
+    x = torch.empty((n_b, n), dtype=torch.complex128, device="cuda")
+    for c, (j, v) in enumerate(cols):
+        x[c].copy_(torch.from_numpy(_plane_wave(dims, j, v)))
+    xb = P.chebfd_pack(M, x.T, n_b)
+    eta, nu = P.chebfd_filter(M, al, be, gam, n_b, n_b, xb)
+    P.chebfd_unpack(M, xb, out=x.T)
+    eta, nu = eta.cpu().numpy(), nu.cpu().numpy()
+    del xb, M
+    lam = np.array(lam)
+    th = np.arccos(lam)
+    Tp = np.cos(np.arange(n_p + 1)[:, None] * th[None, :])          # T_p(lam_c)
+    f = gam @ Tp                                                     # filter value per column
+    n_sites = n // 4
+    u = EPS64 if prec == 0 else EPS32
+    tol_T = _bound(n_p, 13, u, s)
+    tol_Y = max(np.sum(np.abs(gam)), 1.0) * tol_T
+    worst = 0.0
+    for c, (j, v) in enumerate(cols):
+        y = x[c].cpu().numpy()
+        err = np.max(np.abs(y - f[c] * _plane_wave(dims, j, v)))
+        worst = max(worst, err)
+    # eta_p = T_p T_{p-1} |x|^2, nu_p = T_{p-1}^2 |x|^2 with |x|^2 = number of sites
+    eta_ref = Tp[1:] * Tp[:-1] * n_sites
+    nu_ref = Tp[:-1] ** 2 * n_sites
+    tol_m = 2.0 * n * tol_T + n * 4 * u
+    err_e = np.max(np.abs(eta[1:] - eta_ref))
+    err_n = np.max(np.abs(nu[1:] - nu_ref))
+    print(f"# max|Y - f(lam) x| {worst:.3e} (bound {tol_Y:.3e}), eta {err_e:.3e}, nu {err_n:.3e} "
+          f"(bound {tol_m:.3e})", flush=True)
+    assert worst <= tol_Y and err_e <= tol_m and err_n <= tol_m

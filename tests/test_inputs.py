@@ -118,3 +118,20 @@ def test_random_phase_block():
 def test_diag_csr():
     rp, col, val = diag_csr(np.array([1.0, -2.0, 0.5]))
     assert np.array_equal(csr_to_dense(rp, col, val), np.diag([1.0, -2.0, 0.5]).astype(complex))
+
+
+def test_plane_waves_are_eigenvectors_of_the_clean_lattice():
+    """The Bloch vectors of the full-size GPU test: H x = E x for the clean lattice."""
+    import scipy.sparse as sp
+    from tests.test_gpu_fullsize import _bloch_matrix, _plane_wave
+    dims = (5, 4, 6)
+    H = topi_csr(*dims, m=1.0, W=0.0)
+    n = len(H[0]) - 1
+    A = sp.csr_matrix((H[2], H[1], H[0]), shape=(n, n))
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        j = [int(rng.integers(0, N)) for N in dims]
+        E, V = np.linalg.eigh(_bloch_matrix([2 * np.pi * jj / N for jj, N in zip(j, dims)]))
+        for b in range(4):
+            x = _plane_wave(dims, j, V[:, b])
+            assert np.max(np.abs(A @ x - E[b] * x)) < 1e-13

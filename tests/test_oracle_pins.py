@@ -302,6 +302,40 @@ def test_solve_small_configuration_matches_shift_invert():
     assert np.max(res.resid[:res.n_found]) <= 1e-9
 
 
+# Instances whose in-interval Ritz pairs include stable mixtures (residuals just
+# under the half width) beside the converged eigenpairs: the solve must stop once
+# the converged count repeats and those residuals stall, with the exact count.
+STALL_CASES = [
+    # dims, m, W, disorder seed, half width, n_p, n_s, most iterations
+    ((12, 17, 17), 1.5829323234375885, 0.32055382207121985, 1200002, 0.5856721148945054, 559, 64, 8),
+    ((11, 12, 15), 1.8410209481090003, 2.8398561100559334, 1200004, 0.5083305263333662, 342, 96, 12),
+]
+
+
+@pytest.mark.parametrize("dims,m,W,seed,hw,n_p,n_s,max_it", STALL_CASES)
+def test_solve_stops_when_unresolved_pairs_stall(dims, m, W, seed, hw, n_p, n_s, max_it):
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    H = topi_csr(*dims, m=m, W=W, seed=seed)
+    n = len(H[0]) - 1
+    A = sp.csr_matrix((H[2], H[1], H[0]), shape=(n, n)).tocsc()
+    near0 = np.sort(sla.eigsh(A, k=40, sigma=0.0, which="LM", return_eigenvectors=False))
+    assert np.abs(near0).max() > hw          # the 40 nearest include everything inside
+    ref = near0[np.abs(near0) <= hw]
+    tr = []
+    res = O.chebfd_solve(H, -hw, hw, n_s, n_p, 32, random_phase_block(n, n_s, 43 + seed),
+                         refill_seed=43 + seed, max_iter=12, trace=tr)
+    assert res.status == 0 and res.iterations <= max_it
+    assert res.n_found == len(ref) > 0
+    assert np.max(np.abs(np.sort(res.theta[:res.n_found]) - ref)) < 1e-12
+    # the pairs that stopped the iteration: in the interval, unconverged, residuals
+    # that did not halve over the last iteration
+    (_, th1, r1), (_, th2, r2) = tr[-2], tr[-1]
+    un1 = r1[(np.abs(th1) <= hw) & (r1 > 1e-9)]
+    un2 = r2[(np.abs(th2) <= hw) & (r2 > 1e-9)]
+    assert len(un2) == 0 or un2.min() > 0.5 * un1.min()
+
+
 def test_choose_params_reading():
     # heuristic: n_p = kappa / half width, n_s = 2 n_hat rounded up to a block
     assert O.choose_params(-0.01, 0.01, 47.3, 32, kappa=2.0) == (200, 96)

@@ -166,10 +166,20 @@ def random_phase_block(n: int, m: int, seed: int, col0: int = 0) -> np.ndarray:
     base = splitmix64(np.uint64(seed & 0xFFFFFFFFFFFFFFFF))
     out = np.empty((n, m), dtype=np.complex128, order="F")
     i = np.arange(n, dtype=np.uint64)
-    for j in range(m):
+
+    def column(j):
         kj = splitmix64(base ^ np.uint64(col0 + j))
         u = uniform01(kj ^ i)
         out[:, j] = np.exp(2j * np.pi * u)
+
+    if n * m < (1 << 22):
+        for j in range(m):
+            column(j)
+    else:
+        # columns are independent; numpy releases the GIL inside these loops
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(m, 16)) as ex:
+            list(ex.map(column, range(m)))
     return out
 
 
