@@ -374,18 +374,23 @@ def main():
                    "fused_speedup": round(u_step / step_ms, 3)}
         log(f"unfused filter: {u_step:.2f} ms per step (fused {step_ms:.2f} ms: x{u_step / step_ms:.2f})")
 
-    # attainable HBM bandwidth: copy probe over 2 x 2 GiB (the STREAM analogue of Table 2)
-    cnt = 1 << 28
+    # attainable HBM bandwidth (the STREAM analogue of Table 2) over 2 x 4 GiB: the plain
+    # copy, the non-temporal copy (four 16-byte elements per thread) and a read-only pass
+    cnt = 1 << 29
     pa = torch.empty(cnt, dtype=torch.float64, device="cuda")
     pb = torch.ones(cnt, dtype=torch.float64, device="cuda")
-    P.chebfd_probe_stream(0, pa, pb)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(bf.stream)
-    for _ in range(10):
-        P.chebfd_probe_stream(0, pa, pb)
-    e1.record(bf.stream)
-    torch.cuda.synchronize()
-    copy_gbs = 10 * 2 * 8 * cnt / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    probes = {}
+    for kind, name, nbytes in ((0, "copy", 16 * cnt), (2, "copy_nt", 16 * cnt), (3, "read", 8 * cnt)):
+        P.chebfd_probe_stream(kind, pa, pb)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(bf.stream)
+        for _ in range(10):
+            P.chebfd_probe_stream(kind, pa, pb)
+        e1.record(bf.stream)
+        torch.cuda.synchronize()
+        probes[name] = round(10 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    copy_gbs = max(probes["copy"], probes["copy_nt"])
+    log(f"probes: {probes}")
     del pa, pb
     del bf, M
     torch.cuda.empty_cache()
@@ -429,12 +434,12 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             gram_ms = e0.elapsed_time(e1) / 3
-            # useful flops of the Hermitian product: the upper triangle with its diagonal
-            useful = 8.0 * n * ns * (ns + mb) / 2
+            # flops of the Hermitian product's distinct entries (upper triangle and diagonal)
+            useful = 8.0 * n * ns * (ns + 1) / 2
             gram = {"kernel": "gram_kernel (FP64 MFMA 16x16x4)", "shape": f"{n} x {ns} x {ns} complex (c64 in)",
                     "ms": round(gram_ms, 3), "tflops": round(useful / (gram_ms * 1e-3) / 1e12, 2),
                     "frac_of_fp64_mfma_peak": round(useful / (gram_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
-                    "flops_counted": "8 n n_s (n_s + n_b) / 2: the blocks of the upper triangle"}
+                    "flops_counted": "8 n n_s (n_s + 1) / 2: the distinct entries of the Hermitian S"}
             log(f"gram: {gram_ms:.1f} ms, {gram['tflops']} TFLOP/s")
             del Y
         del M32
@@ -494,6 +499,7 @@ def main():
         "pct_of_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
         "gflops": round(gflops, 1),
         "copy_probe_gbs": round(copy_gbs, 1),
+        "stream_probes_gbs": probes,
         "pct_of_copy_probe": round(100.0 * gbs / copy_gbs, 2),
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -264,7 +264,9 @@ int chebfd_kpm_moments(const chebfd_matrix *H, double alpha, double beta, int32_
  * dimension ld >= m1) of two n x m1 and n x m2 block vectors in the blocked
  * layout (block width n_b, precision prec), with FP64 MFMA; the row range is
  * split over workgroups and the partial products are summed in a fixed order.
- * d_work: chebfd_gram_query bytes.
+ * When d_a == d_b and m1 == m2 the product is Hermitian: only the 64 x 64 tiles
+ * on and above the diagonal are formed and the rest of S is their mirror image
+ * (exactly conj-symmetric).  d_work: chebfd_gram_query bytes.
  */
 int chebfd_gram_query(int64_t n, int32_t m1, int32_t m2, size_t *work_bytes);
 int chebfd_gram(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec, const void *d_a,
@@ -432,9 +434,11 @@ int chebfd_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v
                     float beta1, float beta2, float eps, void *stream);
 
 /*
- * HBM bandwidth probe (the STREAM analogue of Sect. 1.2, Table 2): copy
- * (b = a) or triad (a = b + s c) over `count` doubles.  kind 0 = copy,
- * kind 1 = triad.
+ * HBM bandwidth probe (the STREAM analogue of Sect. 1.2, Table 2) over
+ * `count` doubles (even): kind 0 = copy a = b (one 16-byte element per
+ * thread), 1 = triad a = b + s c, 2 = copy a = b with non-temporal loads and
+ * stores, four 16-byte elements per thread, 3 = read-only pass over b (one
+ * sum per workgroup of 1024 doubles written to the front of a).
  */
 int chebfd_probe_stream(int32_t kind, int64_t count, const double *d_b, const double *d_c,
                         double s, double *d_a, void *stream);

@@ -911,10 +911,10 @@ int chebfd_spmmv(const chebfd_matrix *H, double alpha, double beta, int32_t n_b,
 int chebfd_probe_stream(int32_t kind, int64_t count, const double *d_b, const double *d_c, double s,
                         double *d_a, void *stream) {
     clear_error();
-    CHEBFD_REQUIRE(kind == 0 || kind == 1, "kind = %d invalid", kind);
+    CHEBFD_REQUIRE(kind >= 0 && kind <= 3, "kind = %d invalid", kind);
     CHEBFD_REQUIRE(count >= 2 && count % 2 == 0, "count must be even and >= 2");
-    CHEBFD_REQUIRE(d_a && d_b && (kind == 0 || d_c), "NULL buffer");
-    CHEBFD_REQUIRE(aligned(d_a, 16) && aligned(d_b, 16) && (kind == 0 || aligned(d_c, 16)),
+    CHEBFD_REQUIRE(d_a && d_b && (kind != 1 || d_c), "NULL buffer");
+    CHEBFD_REQUIRE(aligned(d_a, 16) && aligned(d_b, 16) && (kind != 1 || aligned(d_c, 16)),
                    "buffers must be 16-byte aligned");
     DeviceProps d;
     int rc = device_props(&d);

@@ -57,20 +57,37 @@ __device__ inline int64_t blocked_index(int64_t n, int nb, int64_t i, int c) {
 // Gram: S(a, b) = sum_i conj(A(i, a)) B(i, b), 64 x 64 complex output tile per
 // workgroup (4 waves, 32 x 32 each = 2 x 2 MFMA tiles x 4 real products), rows
 // [r0, r1) of one split; partial tiles go to part[split][tile] and are summed
-// in split order by gram_reduce_kernel.
+// in split order by gram_reduce_kernel.  For the Hermitian product A^H A only
+// the tiles on and above the diagonal are formed (tile index t enumerates them
+// column by column) and the reduction mirrors them.
 // ---------------------------------------------------------------------------
 constexpr int kGT = 64;   // output tile edge
 constexpr int kGK = 16;   // rows per LDS stage
 
+// (row tile, column tile) of output tile t: column-major over all tiles, or
+// over the upper triangle (row tile <= column tile) when herm
+__device__ inline void gram_tile(int t, int tiles_a, bool herm, int *ta, int *tb) {
+    if (!herm) {
+        *ta = t % tiles_a;
+        *tb = t / tiles_a;
+        return;
+    }
+    int c = 0;
+    while ((c + 1) * (c + 2) / 2 <= t) ++c;
+    *tb = c;
+    *ta = t - c * (c + 1) / 2;
+}
+
 __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int prec_a, int nb_a, const void *B,
                                                    int prec_b, int nb_b, int64_t n, int m1, int m2,
-                                                   int tiles_a, int tiles_b, int64_t rows_per_split,
+                                                   int tiles_a, int herm, int64_t rows_per_split,
                                                    double *part) {
     __shared__ double2 sa[kGK][kGT];
     __shared__ double2 sb[kGK][kGT];
     const int tile = blockIdx.x;
     const int split = blockIdx.y;
-    const int ta = tile % tiles_a, tb = tile / tiles_a;
+    int ta, tb;
+    gram_tile(tile, tiles_a, herm != 0, &ta, &tb);
     const int a0 = ta * kGT, b0 = tb * kGT;
     const int64_t r0 = (int64_t)split * rows_per_split;
     const int64_t r1 = r0 + rows_per_split < n ? r0 + rows_per_split : n;
@@ -155,9 +172,10 @@ __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int prec_a, int
             }
 }
 
-// S = sum over splits (in split order) of the partial tiles; S column-major, ld
+// S = sum over splits (in split order) of the partial tiles; S column-major, ld.
+// herm: tiles above the diagonal also give their mirror image S(b, a) = conj S(a, b).
 __global__ __launch_bounds__(kT) void gram_reduce_kernel(const double *part, int nsplit, int ntiles,
-                                                         int tiles_a, int m1, int m2, double *S,
+                                                         int tiles_a, int herm, int m1, int m2, double *S,
                                                          int ld) {
     const int64_t total = (int64_t)ntiles * kGT * kGT;
     const double2 *p = reinterpret_cast<const double2 *>(part);
@@ -165,7 +183,9 @@ __global__ __launch_bounds__(kT) void gram_reduce_kernel(const double *part, int
         const int tile = static_cast<int>(t / (kGT * kGT));
         const int e = static_cast<int>(t % (kGT * kGT));
         const int ra = e % kGT, cb = e / kGT;
-        const int a = (tile % tiles_a) * kGT + ra, b = (tile / tiles_a) * kGT + cb;
+        int ta, tb;
+        gram_tile(tile, tiles_a, herm != 0, &ta, &tb);
+        const int a = ta * kGT + ra, b = tb * kGT + cb;
         if (a >= m1 || b >= m2) continue;
         double sr = 0.0, si = 0.0;
         for (int s = 0; s < nsplit; ++s) {
@@ -174,6 +194,7 @@ __global__ __launch_bounds__(kT) void gram_reduce_kernel(const double *part, int
             si += v.y;
         }
         reinterpret_cast<double2 *>(S)[(int64_t)b * ld + a] = double2{sr, si};
+        if (herm && ta != tb) reinterpret_cast<double2 *>(S)[(int64_t)a * ld + b] = double2{sr, -si};
     }
 }
 
@@ -653,14 +674,17 @@ __global__ __launch_bounds__(kT) void scale_columns_kernel(void *Z, int prec, in
 int launch_gram(const void *A, int prec_a, int nb_a, const void *B, int prec_b, int nb_b, int64_t n,
                 int m1, int m2, double *part, int nsplit, double *S, int ld, hipStream_t s) {
     const int ta = (m1 + kGT - 1) / kGT, tb = (m2 + kGT - 1) / kGT;
+    // A^H A: Hermitian, only the tiles on and above the diagonal
+    const int herm = (A == B && prec_a == prec_b && nb_a == nb_b && m1 == m2) ? 1 : 0;
+    const int ntiles = herm ? ta * (ta + 1) / 2 : ta * tb;
     const int64_t rps = ((n + nsplit - 1) / nsplit + kGK - 1) / kGK * kGK;
-    hipLaunchKernelGGL(gram_kernel, dim3(ta * tb, nsplit), dim3(kT), 0, s, A, prec_a, nb_a, B, prec_b, nb_b,
-                       n, m1, m2, ta, tb, rps, part);
+    hipLaunchKernelGGL(gram_kernel, dim3(ntiles, nsplit), dim3(kT), 0, s, A, prec_a, nb_a, B, prec_b, nb_b,
+                       n, m1, m2, ta, herm, rps, part);
     CHEBFD_HIP(hipGetLastError());
-    const int64_t total = (int64_t)ta * tb * kGT * kGT;
+    const int64_t total = (int64_t)ntiles * kGT * kGT;
     int G = static_cast<int>((total + kT - 1) / kT);
     if (G > 4096) G = 4096;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(G), dim3(kT), 0, s, part, nsplit, ta * tb, ta, m1, m2,
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(G), dim3(kT), 0, s, part, nsplit, ntiles, ta, herm, m1, m2,
                        S, ld);
     CHEBFD_HIP(hipGetLastError());
     return CHEBFD_OK;

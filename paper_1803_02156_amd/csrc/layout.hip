@@ -204,13 +204,65 @@ __global__ __launch_bounds__(kT) void triad_kernel(int64_t n2, const double2 *__
     }
 }
 
+// Copy with non-temporal loads and stores, kU 16-byte elements per thread
+// (consecutive threads take consecutive elements within each of the kU rounds).
+constexpr int kU = 4;
+typedef double dv2p __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(kT) void copy_nt_kernel(int64_t n2, const dv2p *__restrict__ b, dv2p *__restrict__ a) {
+    const int64_t base = (int64_t)blockIdx.x * kT * kU + threadIdx.x;
+    dv2p v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int64_t t = base + (int64_t)u * kT;
+        if (t < n2) v[u] = __builtin_nontemporal_load(b + t);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int64_t t = base + (int64_t)u * kT;
+        if (t < n2) __builtin_nontemporal_store(v[u], a + t);
+    }
+}
+
+// Read-only stream: per-workgroup sums of b (written to a[blockIdx.x]).
+__global__ __launch_bounds__(kT) void read_kernel(int64_t n2, const dv2p *__restrict__ b, double *a) {
+    __shared__ double sh[kT];
+    const int64_t base = (int64_t)blockIdx.x * kT * kU + threadIdx.x;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int64_t t = base + (int64_t)u * kT;
+        if (t < n2) {
+            const dv2p v = __builtin_nontemporal_load(b + t);
+            acc += v.x + v.y;
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a[blockIdx.x] = sh[0];
+}
+
 int launch_stream_probe(int kind, int64_t count, const double *b, const double *c, double sc,
                         double *a, int num_cus, hipStream_t s) {
     const int64_t n2 = count / 2;
-    // one 16-byte element per thread over a flat grid: the launch shape that
-    // reaches the highest streaming rate on this device (a persistent
-    // grid-stride loop of the same copy stays well below it)
     (void)num_cus;
+    if (kind == 2 || kind == 3) {
+        int64_t G = (n2 + (int64_t)kT * kU - 1) / ((int64_t)kT * kU);
+        if (G > 0x7fffffff) G = 0x7fffffff;
+        if (kind == 2)
+            hipLaunchKernelGGL(copy_nt_kernel, dim3(G), dim3(kT), 0, s, n2, reinterpret_cast<const dv2p *>(b),
+                               reinterpret_cast<dv2p *>(a));
+        else
+            hipLaunchKernelGGL(read_kernel, dim3(G), dim3(kT), 0, s, n2, reinterpret_cast<const dv2p *>(b), a);
+        CHEBFD_HIP(hipGetLastError());
+        return CHEBFD_OK;
+    }
+    // one 16-byte element per thread over a flat grid: the launch shape that
+    // reaches the highest streaming rate of the plain copy on this device (a
+    // persistent grid-stride loop of the same copy stays well below it)
     int64_t G = (n2 + kT - 1) / kT;
     if (G > 0x7fffffff) G = 0x7fffffff;
     if (G < 1) G = 1;
