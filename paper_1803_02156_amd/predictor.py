@@ -110,10 +110,19 @@ def run(M, inst: Instance, n_p: int, n_s: int, max_iter: int = 12):
     return r, time.perf_counter() - t0
 
 
-def grid(heur_np: int, heur_ns: int):
-    nps = sorted({int(min(_abi.NP_MAX, max(_abi.NP_MIN, round(heur_np * f)))) for f in (1.0, 2.0, 4.0, 8.0)})
-    nss = sorted({heur_ns, min(512, heur_ns + N_B)})
-    return [(a, b) for a in nps for b in nss]
+NP_FACTORS = (0.5, 1.0, 2.0, 4.0)
+
+
+def grid(heur_np: int, heur_ns: int, count_est: float = 0.0):
+    """Label grid around the heuristic's (n_p, n_s): n_p times 0.5, 1, 2, 4 and n_s
+    one block below (when that still holds 1.2 n_hat and one block), at and one
+    block above the heuristic's, clamped to the parameter rule's ranges."""
+    nps = sorted({int(min(_abi.NP_MAX, max(_abi.NP_MIN, round(heur_np * f)))) for f in NP_FACTORS})
+    nss = {heur_ns, min(512, heur_ns + N_B)}
+    lower = heur_ns - N_B
+    if lower >= max(N_B, math.ceil(1.2 * max(count_est, 0.0))):
+        nss.add(lower)
+    return [(a, b) for a in nps for b in sorted(nss)]
 
 
 def next_adaptive_np(n_p: int, found: list, np_cap: int):
@@ -171,7 +180,7 @@ def make_corpus(count: int, seed: int, ext_lo: int, ext_hi: int, kappa: float, c
                 found.append(results[-1]["n_found"])
                 n_p = next_adaptive_np(n_p, found, np_cap)
         else:
-            for n_p, n_s in grid(hp, hs):
+            for n_p, n_s in grid(hp, hs, cnt):
                 solve(n_p, n_s)
         full = max(x["n_found"] for x in results)
         ok = [x for x in results if x["status"] == 0 and x["n_found"] == full]
@@ -298,6 +307,7 @@ def evaluate(pred: dict, corpus: list, kappa: float, log=print):
             r, dt = run(M, inst, n_p, n_s)
             res[name] = dict(n_p=n_p, n_s=n_s, status=r.status, iters=r.stats.iterations, n_found=r.n_found,
                              seconds=dt, work=work_units(M.n, len(H[1]), n_p, n_s, r.stats.iterations),
+                             full_count_found=bool(r.n_found >= row["full_count"]),
                              failed=bool(r.status != 0 or r.n_found < row["full_count"]))
         out.append(dict(inst=row["inst"], full_count=row["full_count"], **res))
         log(f"# eval {k + 1}/{len(corpus)}: heur {res['heuristic']['n_p']},{res['heuristic']['n_s']} "
@@ -312,6 +322,9 @@ def summarise(ev: list) -> dict:
     s = {"instances": len(ev)}
     for name in ("heuristic", "mlp"):
         s[name] = {"failures": int(sum(e[name]["failed"] for e in ev)),
+                   "full_count_found": int(sum(e[name].get("full_count_found", not e[name]["failed"]) for e in ev)),
+                   "not_converged": int(sum(e[name]["status"] != 0 for e in ev)) if all("status" in e[name] for e in ev)
+                   else None,
                    "mean_iters": float(col(name, "iters").mean()),
                    "total_seconds": float(col(name, "seconds").sum()),
                    "total_work": float(col(name, "work").sum())}

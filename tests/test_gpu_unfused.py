@@ -80,9 +80,10 @@ def _filter_and_compare(P, H, prec, n_b, n_s, n_p, C, sigma, want_kind, unfused,
     tol_T = _bound(n_p, nnzr, u, min(s, 0.999))
     tol_Y = max(np.sum(np.abs(gam)), 1.0) * tol_T
     assert np.max(np.abs(Y - Yr)) <= tol_Y, (np.max(np.abs(Y - Yr)), tol_Y)
-    tol_m = 2.0 * n * tol_T + n * 4 * u
-    assert np.max(np.abs(eta[1:] - etar[1:])) <= tol_m
-    assert np.max(np.abs(nu[1:] - nur[1:].real)) <= tol_m
+    if n_p >= 1:   # (degree 0 forms no moments)
+        tol_m = 2.0 * n * tol_T + n * 4 * u
+        assert np.max(np.abs(eta[1:] - etar[1:])) <= tol_m
+        assert np.max(np.abs(nu[1:] - nur[1:].real)) <= tol_m
     return Y, eta, nu
 
 

@@ -17,10 +17,13 @@ def test_sampled_instances_cover_the_stated_ranges():
 
 
 def test_grid_is_clamped_and_contains_the_heuristic():
-    g = PR.grid(400, 64)
-    assert (400, 64) in g and (800, 96) in g and (1600, 64) in g and (3200, 96) in g and len(g) == 8
-    g = PR.grid(30, 512)
-    assert all(50 <= a <= 20000 and b <= 512 for a, b in g) and (50, 512) in g and (240, 512) in g
+    g = PR.grid(400, 64, 20.0)
+    assert set(g) == {(a, b) for a in (200, 400, 800, 1600) for b in (32, 64, 96)}
+    g = PR.grid(400, 64, 30.0)           # 1.2 n_hat = 36 > 32: no smaller subspace
+    assert set(g) == {(a, b) for a in (200, 400, 800, 1600) for b in (64, 96)}
+    g = PR.grid(30, 512, 200.0)
+    assert all(50 <= a <= 20000 and b <= 512 for a, b in g) and (50, 512) in g and (120, 480) in g
+    assert len(g) == 2 * 3
 
 
 def test_standardise_round_trip():
