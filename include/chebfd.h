@@ -223,6 +223,25 @@ int chebfd_filter_unfused(const chebfd_matrix *H, double alpha, double beta, con
                           void *stream);
 
 /*
+ * chebfd_filter without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the partial dot-product sums that the step kernels
+ * hand from one launch to the next live in a static device array of 4 MiB
+ * (one copy per device, held until the process ends).  Every call on a device
+ * shares that device's array: calls that overlap on one device (on different
+ * streams, or from several threads) race; calls in sequence on a stream are
+ * safe, since each launch overwrites the partials it later reads and nothing
+ * has to start at zero.  Returns CHEBFD_EWORKSPACE, touching nothing, when
+ * the launch geometry for H and n_b needs more than the array holds
+ * (chebfd_filter_query bytes > 4 MiB: large n_b with many resident
+ * workgroups).  Allocates nothing; other arguments, results and errors as
+ * chebfd_filter (the same kernels in the same order: bitwise equal results).
+ */
+int chebfd_filter_noalloc(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
+                          int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
+                          void *d_w, double *d_eta, double *d_nu, void *stream);
+
+/*
  * One fused Chebyshev step on one block, as timed by the benchmarks (the
  * recurrence step of Alg. 1): W <- 2(alpha H + beta I) U - W in place, eta_p = <W, U>,
  * mu_p = <U, U>, Y <- Y + gamma W.  Same layouts and workspace as

@@ -224,6 +224,16 @@ def chebfd_filter_unfused(H: Matrix, alpha: float, beta: float, gamma, n_s: int,
     return eta, nu
 
 
+def chebfd_filter_noalloc(H: Matrix, alpha: float, beta: float, gamma, n_s: int, n_b: int, xy: torch.Tensor,
+                          u: torch.Tensor, w: torch.Tensor, eta: torch.Tensor | None, nu: torch.Tensor | None):
+    """chebfd_filter with the library's static scratch instead of a workspace; every
+    buffer is the caller's (this call allocates nothing)."""
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+    check(load().chebfd_filter_noalloc(H.ref(), alpha, beta, gamma.ctypes.data_as(ctypes.c_void_p),
+                                       len(gamma) - 1, n_s, n_b, H.prec, _ptr(xy), _ptr(u), _ptr(w), _ptr(eta),
+                                       _ptr(nu), _stream()))
+
+
 def chebfd_op(H: Matrix, alpha: float, beta: float, gamma: float, n_b: int, u, w, y, work: torch.Tensor,
               work_bytes: int):
     check(load().chebfd_op(H.ref(), alpha, beta, gamma, n_b, H.prec, _ptr(u), _ptr(w), _ptr(y),

@@ -52,6 +52,30 @@ int device_props(DeviceProps *out) {
     return CHEBFD_OK;
 }
 
+// Static scratch of chebfd_filter_noalloc: the partial dot-product sums the step
+// kernels pass from one launch to the next.  Each device holds its own copy
+// until the process ends.  Host code never uses the array's name as a device
+// address: scratch_ptr() looks the copy of the current device up once.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static int scratch_ptr(void **out) {
+    static std::mutex mu;
+    static void *ptr[64] = {};
+    int dev = 0;
+    CHEBFD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) CHEBFD_FAIL(CHEBFD_EHIP, "device id %d out of range", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (ptr[dev] == nullptr) {
+        void *p = nullptr;
+        CHEBFD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (p == nullptr) CHEBFD_FAIL(CHEBFD_EHIP, "no device address for the static scratch buffer");
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return CHEBFD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // SELL-C-sigma layout on the host
 // ---------------------------------------------------------------------------
@@ -586,6 +610,30 @@ int chebfd_filter(const chebfd_matrix *H, double alpha, double beta, const doubl
 static int filter_unfused_run(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma, int n_p,
                               int n_s, int n_b, int prec, void *d_xy, void *d_u, void *d_w, double *d_eta,
                               double *d_nu, void *d_work, const StepGeometry &geo, hipStream_t s);
+
+int chebfd_filter_noalloc(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
+                          int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
+                          void *d_w, double *d_eta, double *d_nu, void *stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_handle(H)) || (rc = check_prec_nb(prec, n_b))) return rc;
+    StepGeometry geo;
+    if ((rc = filter_geometry(H, prec, n_b, &geo))) return rc;
+    const size_t need = filter_work_bytes(n_b, geo.G);
+    if (need > kNoAllocScratchBytes)
+        CHEBFD_FAIL(CHEBFD_EWORKSPACE,
+                    "n_b = %d needs %zu bytes of partial sums here; the static scratch holds %zu "
+                    "(use chebfd_filter with a workspace)",
+                    n_b, need, kNoAllocScratchBytes);
+    void *work = nullptr;
+    if ((rc = scratch_ptr(&work))) return rc;
+    size_t need2 = 0;
+    if ((rc = check_filter_args(H, alpha, beta, h_gamma, n_p, n_s, n_b, prec, d_xy, d_u, d_w, d_eta, d_nu, work,
+                                kNoAllocScratchBytes, &geo, &need2)))
+        return rc;
+    return filter_run(H, alpha, beta, h_gamma, n_p, n_s, n_b, prec, d_xy, d_u, d_w, d_eta, d_nu, work, need2, geo,
+                      false, static_cast<hipStream_t>(stream));
+}
 
 int chebfd_filter_unfused(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma,
                           int32_t n_p, int32_t n_s, int32_t n_b, int32_t prec, void *d_xy, void *d_u,
