@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--solve-count", type=float, default=100.0,
                     help="eigenvalue count the symmetric search interval is sized for")
     ap.add_argument("--solve-n_b", type=int, default=32)
+    ap.add_argument("--beyond-hbm-lattice", type=str, default="128x128x64",
+                    help="lattice of the host-resident search-space leg ('' skips it)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="target CPU time of each oracle sample (0 disables)")
     return ap.parse_args()
@@ -233,6 +235,50 @@ def time_to_converged(P, lattice, W, n_b, target):
         o["speedup_vs_fp64_heuristic"] = round(out["fp64_heuristic"]["seconds"] / o["seconds"], 3)
     del M64, M32
     return out, H
+
+
+def beyond_hbm(P, lattice, n_b=32, n_s=128, degrees=(10, 30, 100)):
+    """The filter on a search space held in pinned host memory (blocks streamed
+    through two device staging blocks, Sect. 3.5 / Fig. 6) against the same
+    filter on a device-resident search space, for several filter degrees."""
+    import torch
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    from topi import topi_csr
+    Nx, Ny, Nz = (int(v) for v in lattice.split("x"))
+    H = topi_csr(Nx, Ny, Nz, m=1.0, W=1.0, t=1.0, seed=1002)
+    M = P.chebfd_matrix_build(*H, prec=0, order=lattice_row_order(Nx, Ny, Nz))
+    del H
+    lo, hi = P.chebfd_bounds(M)
+    xd = P.chebfd_random_phase(M, n_s, n_b, 45)
+    xh = torch.empty(xd.shape, dtype=xd.dtype, pin_memory=True)
+    xh.copy_(xd)
+    x0 = xd.clone()
+    out = {"workload": f"Topi-{Nx}-{Ny}-{Nz} (n={M.n}), FP64, n_s={n_s} ({n_s // n_b} blocks of n_b={n_b}, "
+                       f"{xh.numel() * 16 / 2**30:.1f} GiB in pinned host memory)", "runs": []}
+    for n_p in degrees:
+        al, be, gam = P.chebfd_coefficients(lo, hi, -0.1, 0.1, n_p)
+        work = P.FilterWork(M, n_b, n_p, n_s, moments=True)
+        P.chebfd_filter(M, al, be, gam, n_s, n_b, xd, work=work)     # warm-up
+        xd.copy_(x0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.chebfd_filter(M, al, be, gam, n_s, n_b, xd, work=work)
+        torch.cuda.synchronize()
+        t_dev = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        P.chebfd_filter_streamed(M, al, be, gam, n_s, n_b, xh)
+        torch.cuda.synchronize()
+        t_host = time.perf_counter() - t0
+        same = bool(torch.equal(xh, xd.cpu()))
+        xh.copy_(x0)
+        xd.copy_(x0)
+        out["runs"].append({"n_p": n_p, "device_s": round(t_dev, 4), "host_resident_s": round(t_host, 4),
+                            "slowdown": round(t_host / t_dev, 3), "equal_results": same})
+        log(f"beyond HBM n_p={n_p}: device {t_dev:.3f} s, host-resident {t_host:.3f} s")
+        del work
+    del xd, xh, x0, M
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_info():
@@ -452,6 +498,10 @@ def main():
         solve, H_small = time_to_converged(P, args.solve_lattice, args.solve_W, args.solve_n_b, args.solve_count)
         torch.cuda.empty_cache()
 
+    hostres = None
+    if args.beyond_hbm_lattice:
+        hostres = beyond_hbm(P, args.beyond_hbm_lattice)
+
     cpu = None
     if args.cpu_baseline_seconds > 0:
         try:
@@ -514,6 +564,7 @@ def main():
         "filter_mixed": mixed,
         "gram": gram,
         "time_to_converged": solve,
+        "beyond_hbm": hostres,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -242,6 +242,28 @@ int chebfd_filter_noalloc(const chebfd_matrix *H, double alpha, double beta, con
                           void *d_w, double *d_eta, double *d_nu, void *stream);
 
 /*
+ * The filter on a search space held in host memory, for working sets larger
+ * than the device memory (Sect. 3.5, Fig. 6: each block is loaded once and
+ * then filtered for n_p steps, so the transfers are amortised over n_p).
+ * h_xy: pinned host memory (hipHostMalloc or equivalent; pageable memory works
+ * but its copies do not overlap) in the blocked layout of chebfd_pack, n_s
+ * vectors of precision `prec`; X on entry, Y once `stream` has completed.
+ * The blocks pass through two device staging blocks in d_work: block b + 1 is
+ * copied in on `copy_stream` while block b is filtered on `stream` (with
+ * chebfd_filter: same kernels, bitwise equal results), and block b is copied
+ * back on `copy_stream` once its filter is done; `stream` finally waits for
+ * the last copy.  d_u, d_w: n x n_b work blocks; d_eta, d_nu as chebfd_filter
+ * (device memory, may be NULL together); d_work: chebfd_filter_streamed_query
+ * bytes (two blocks of n x n_b, the moments of one block and the filter's
+ * workspace), 256-byte aligned.  copy_stream must differ from stream and both
+ * must belong to the current device.  Errors as chebfd_filter.
+ */
+int chebfd_filter_streamed_query(const chebfd_matrix *H, int32_t n_p, int32_t n_b, size_t *work_bytes);
+int chebfd_filter_streamed(const chebfd_matrix *H, double alpha, double beta, const double *h_gamma, int32_t n_p,
+                           int32_t n_s, int32_t n_b, int32_t prec, void *h_xy, void *d_u, void *d_w, double *d_eta,
+                           double *d_nu, void *d_work, size_t work_bytes, void *stream, void *copy_stream);
+
+/*
  * One fused Chebyshev step on one block, as timed by the benchmarks (the
  * recurrence step of Alg. 1): W <- 2(alpha H + beta I) U - W in place, eta_p = <W, U>,
  * mu_p = <U, U>, Y <- Y + gamma W.  Same layouts and workspace as

@@ -72,6 +72,8 @@ SIGNATURES = {
     "chebfd_filter": (ctypes.c_int, [MP, f64, f64, P, i32, i32, i32, i32, P, P, P, P, P, P, sz, P]),
     "chebfd_filter_unfused": (ctypes.c_int, [MP, f64, f64, P, i32, i32, i32, i32, P, P, P, P, P, P, sz, P]),
     "chebfd_filter_noalloc": (ctypes.c_int, [MP, f64, f64, P, i32, i32, i32, i32, P, P, P, P, P, P]),
+    "chebfd_filter_streamed_query": (ctypes.c_int, [MP, i32, i32, ctypes.POINTER(sz)]),
+    "chebfd_filter_streamed": (ctypes.c_int, [MP, f64, f64, P, i32, i32, i32, i32, P, P, P, P, P, P, sz, P, P]),
     "chebfd_op": (ctypes.c_int, [MP, f64, f64, f64, i32, i32, P, P, P, P, sz, P]),
     "chebfd_spmmv": (ctypes.c_int, [MP, f64, f64, i32, i32, P, P, P, sz, P]),
     "chebfd_kpm_query": (ctypes.c_int, [MP, i32, i32, ctypes.POINTER(sz)]),

@@ -234,6 +234,34 @@ def chebfd_filter_noalloc(H: Matrix, alpha: float, beta: float, gamma, n_s: int,
                                        _ptr(nu), _stream()))
 
 
+def chebfd_filter_streamed(H: Matrix, alpha: float, beta: float, gamma, n_s: int, n_b: int, h_xy: torch.Tensor,
+                           moments: bool = True, copy_stream=None):
+    """Filter the blocked search space h_xy held in (pinned) host memory in place; two
+    device staging blocks, copies on `copy_stream` (a new stream if None); returns
+    (eta, nu) device tensors or (None, None).  Synchronise torch's current stream
+    before reading h_xy."""
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+    n_p = len(gamma) - 1
+    if h_xy.is_cuda or h_xy.dtype != vec_dtype(H.prec) or h_xy.numel() != H.n * n_s or not h_xy.is_contiguous():
+        raise ValueError("h_xy must be a contiguous host tensor of n * n_s elements in the matrix precision")
+    dev = H.buf.device
+    dt = vec_dtype(H.prec)
+    u = torch.empty((H.n, n_b), dtype=dt, device=dev)
+    w = torch.empty((H.n, n_b), dtype=dt, device=dev)
+    sz = ctypes.c_size_t()
+    check(load().chebfd_filter_streamed_query(H.ref(), n_p, n_b, ctypes.byref(sz)))
+    work = device_buffer(sz.value, dev)
+    eta = torch.zeros((n_p + 1, n_s), dtype=torch.complex128, device=dev) if moments else None
+    nu = torch.zeros((n_p + 1, n_s), dtype=torch.float64, device=dev) if moments else None
+    xs = torch.cuda.Stream(device=dev) if copy_stream is None else copy_stream
+    check(load().chebfd_filter_streamed(H.ref(), alpha, beta, gamma.ctypes.data_as(ctypes.c_void_p), n_p, n_s,
+                                        n_b, H.prec, ctypes.c_void_p(h_xy.data_ptr()), _ptr(u), _ptr(w), _ptr(eta),
+                                        _ptr(nu), _ptr(work), sz.value, _stream(), ctypes.c_void_p(xs.cuda_stream)))
+    # keep the device buffers alive until the stream has passed them
+    torch.cuda.current_stream().synchronize()
+    return eta, nu
+
+
 def chebfd_op(H: Matrix, alpha: float, beta: float, gamma: float, n_b: int, u, w, y, work: torch.Tensor,
               work_bytes: int):
     check(load().chebfd_op(H.ref(), alpha, beta, gamma, n_b, H.prec, _ptr(u), _ptr(w), _ptr(y),

@@ -31,8 +31,13 @@ size_t al(size_t v) { return round_up(v, 256); }
 // tolerance independent of m would never be met.
 double jacobi_tol(int m) { return 4.0 * std::max(m, 1) * 0x1.0p-53; }
 
-int gram_splits(int64_t n) {
-    return static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, n / 256)));
+// Row splits of a Gram product S = A^H B (m1 x m2): enough workgroups for a few
+// full waves of the device (about 4096 64 x 64 tile-splits; the Hermitian
+// product forms about half of them) but at least 256 rows per split.
+int gram_splits(int64_t n, int m1, int m2) {
+    const int64_t tiles = (int64_t)((m1 + 63) / 64) * ((m2 + 63) / 64);
+    const int64_t want = (4096 + tiles - 1) / tiles;
+    return static_cast<int>(std::min<int64_t>(std::min<int64_t>(want, 1024), std::max<int64_t>(1, n / 256)));
 }
 
 struct SolveLayout {
@@ -57,7 +62,14 @@ int solve_layout(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
         if ((rc = chebfd_filter_query(H64, p->n_b / 2, &f3))) return rc;
         L->fwork_bytes = std::max(L->fwork_bytes, f3);
     }
-    L->gpart_bytes = gram_part_bytes(p->n_s, p->n_s, gram_splits(H->n));
+    // the largest partial buffer of any Gram product the iteration forms (SVQB:
+    // m x m with m <= n_s kept directions; Rayleigh-Ritz: m x n_b or n_b / 2)
+    L->gpart_bytes = 0;
+    const int tmax = (p->n_s + 63) / 64;
+    for (int ta = 1; ta <= tmax; ++ta)
+        for (int tb = 1; tb <= tmax; ++tb)
+            L->gpart_bytes = std::max(L->gpart_bytes,
+                                      gram_part_bytes(64 * ta, 64 * tb, gram_splits(H->n, 64 * ta, 64 * tb)));
     L->rgrid = resid_grid(H->n);
     L->rpart_bytes = (size_t)2 * nb * L->rgrid * 8;
     if ((rc = chebfd_heev_query(p->n_s, &L->jwork_bytes))) return rc;
@@ -133,7 +145,7 @@ extern "C" {
 int chebfd_gram_query(int64_t n, int32_t m1, int32_t m2, size_t *work_bytes) {
     clear_error();
     CHEBFD_REQUIRE(n >= 1 && m1 >= 1 && m2 >= 1 && work_bytes, "invalid Gram sizes");
-    *work_bytes = gram_part_bytes(m1, m2, gram_splits(n));
+    *work_bytes = gram_part_bytes(m1, m2, gram_splits(n, m1, m2));
     return CHEBFD_OK;
 }
 
@@ -150,7 +162,7 @@ int chebfd_gram(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec, co
     if (rc) return rc;
     if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "Gram workspace %zu < %zu", work_bytes, need);
     return launch_gram(d_a, prec, n_b, d_b, prec, n_b, n, m1, m2, static_cast<double *>(d_work),
-                       gram_splits(n), d_s, ld, static_cast<hipStream_t>(stream));
+                       gram_splits(n, m1, m2), d_s, ld, static_cast<hipStream_t>(stream));
 }
 
 int chebfd_update(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec_a, const void *d_a,
@@ -274,7 +286,7 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     // one SVQB step on the stage's basis: A (m columns) -> B (k kept columns)
     auto svqb = [&](const Stage &g, void *A, int m, void *B, int *k) -> int {
         int r;
-        if ((r = launch_gram(A, g.prec, g.nb, A, g.prec, g.nb, n, m, m, DD(L.gpart), gram_splits(n), DD(L.S), ns,
+        if ((r = launch_gram(A, g.prec, g.nb, A, g.prec, g.nb, n, m, m, DD(L.gpart), gram_splits(n, m, m), DD(L.S), ns,
                              s)))
             return r;
         if ((r = launch_svqb_scale(m, DD(L.S), ns, DD(L.d), s))) return r;
@@ -357,7 +369,7 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
                     return r;
                 const int cols = std::min(g.nb, k2 - b * g.nb);
                 if ((r = launch_gram(g.X, g.prec, g.nb, D(L.t64), CHEBFD_PREC_FP64, g.nb, n, k2, cols, DD(L.gpart),
-                                     gram_splits(n), DD(L.G) + 2 * (size_t)b * g.nb * ns, ns, s)))
+                                     gram_splits(n, k2, cols), DD(L.G) + 2 * (size_t)b * g.nb * ns, ns, s)))
                     return r;
             }
             if ((r = launch_hermitise(k2, DD(L.G), ns, s))) return r;
