@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -135,7 +136,9 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
     const int32_t *__restrict__ gcol = a.col;
     const T alpha = static_cast<T>(a.alpha), beta = static_cast<T>(a.beta);
     const T g0 = static_cast<T>(a.g0), g1 = static_cast<T>(a.g1), g2 = static_cast<T>(a.g2);
-    const int64_t nblk = (a.n + TR - 1) / TR;
+    // row and tile indices fit 32 bits (n < 2^31): scalar loop control stays in SGPRs
+    const int n32 = static_cast<int>(a.n);
+    const int nblk = (n32 + TR - 1) / TR;
 
     double e_re[CPL], e_im[CPL], nu[CPL];
 #pragma unroll
@@ -143,15 +146,15 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
 
     // contiguous tile range of this workgroup; each XCD sweeps one eighth
     const int G = gridDim.x, w = blockIdx.x;
-    int64_t tb, te;
+    int tb, te;
     if (G % kXcdCount == 0) {
         const int x = w % kXcdCount, k = w / kXcdCount, per = G / kXcdCount;
         const int64_t xb = ntiles * x / kXcdCount, xe = ntiles * (x + 1) / kXcdCount;
-        tb = xb + (xe - xb) * k / per;
-        te = xb + (xe - xb) * (k + 1) / per;
+        tb = static_cast<int>(xb + (xe - xb) * k / per);
+        te = static_cast<int>(xb + (xe - xb) * (k + 1) / per);
     } else {
-        tb = ntiles * w / G;
-        te = ntiles * (w + 1) / G;
+        tb = static_cast<int>(ntiles * w / G);
+        te = static_cast<int>(ntiles * (w + 1) / G);
     }
 
     // matrix slots of one tile: one slot per thread (prefetch register, then LDS)
@@ -171,9 +174,12 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
             pf_s0 = a.chunk_off[c0];
             pf_ns = static_cast<int>(a.chunk_off[c1] - pf_s0);
         }
+        // non-temporal: each slot is read once, and keeping the slots out of L2
+        // leaves room for the U rows that neighbouring workgroups gather a few
+        // tiles after they were loaded (the gathers that leave the window)
         if (tid < pf_ns) {
-            pv = gval[pf_s0 + tid];
-            pc = gcol[pf_s0 + tid];
+            pv = ld_nt(gval + pf_s0 + tid);
+            pc = __builtin_nontemporal_load(gcol + pf_s0 + tid);
         }
     };
     auto deposit_mat = [&](int64_t tile, int b) {
@@ -190,7 +196,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
         }
     };
     // one block of U rows: row blk * TR + rr, this lane's columns
-    auto ring_store = [&](int64_t blk, const PK &v) {
+    auto ring_store = [&](int blk, const PK &v) {
         T *dst = reinterpret_cast<T *>(smem + ((blk * TR + rr) & (S::RING_ROWS - 1)) * RB + lane_off);
         if constexpr (CPL == 2) {
             *reinterpret_cast<float4 *>(dst) = float4{v.re[0], v.im[0], v.re[1], v.im[1]};
@@ -198,7 +204,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
             *reinterpret_cast<VT *>(dst) = VT{v.re[0], v.im[0]};
         }
     };
-    auto row_ok = [&](int64_t blk) { return blk >= 0 && blk < nblk && blk * TR + rr < a.n; };
+    auto row_ok = [&](int blk) { return blk >= 0 && blk < nblk && blk * TR + rr < n32; };
 
 
     // (the reduction above ends with a barrier: the ring area is free)
@@ -207,48 +213,61 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
         PK pro[2 * kWinHalo + 1];
 #pragma unroll
         for (int q = 0; q < 2 * kWinHalo + 1; ++q) {
-            const int64_t blk = tb - kWinHalo + q;
-            if (row_ok(blk)) pro[q] = load_pack<T, CPL, false>(P + 2 * ((blk * TR + rr) * NB + jc));
+            const int blk = tb - kWinHalo + q;
+            if (row_ok(blk)) pro[q] = load_pack<T, CPL, false>(P + 2 * ((int64_t)(blk * TR + rr) * NB + jc));
         }
         fetch_mat(tb);
 #pragma unroll
         for (int q = 0; q < 2 * kWinHalo + 1; ++q) {
-            const int64_t blk = tb - kWinHalo + q;
+            const int blk = tb - kWinHalo + q;
             if (row_ok(blk)) ring_store(blk, pro[q]);
         }
         deposit_mat(tb, 0);
     }
     __syncthreads();
 
+    // One tile.  FULL: every row of the tile exists (all tiles but a ragged last
+    // one), so every lane runs the same instruction stream; the partial tile guards
+    // its rows.  (The compiler's wait counts are path-insensitive: a load whose use
+    // sits under a lane-dependent branch stays "pending" at the loop's back edge,
+    // and the next tile then drains the whole memory pipeline before its loads.)
     int buf = 0;
-    for (int64_t tile = tb; tile < te; ++tile) {
+    // The previous tile's stored values, kept live (an empty asm statement uses
+    // them) until this tile's loads are issued: otherwise the register allocator
+    // reuses the store's data registers for this tile's gathers, and the compiler
+    // then waits for the store to complete before issuing the next gathers.
+    PK held_w, held_y;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) held_w.re[c] = held_w.im[c] = held_y.re[c] = held_y.im[c] = T(0);
+    auto tile_body = [&](int tile, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
         const bool more = tile + 1 < te;
-        const int64_t t0 = tile * TR;
-        const int64_t i = t0 + rr;
-        const int wlo = static_cast<int>(t0) - kWinHalo * TR;   // window [wlo, wlo + (2 kWinHalo + 1) TR)
+        const int t0 = tile * TR;
+        const int i = t0 + rr;
+        const bool live = FULL || i < n32;
+        const int wlo = t0 - kWinHalo * TR;   // window [wlo, wlo + (2 kWinHalo + 1) TR)
         const VT *sv = CHEBFD_WV(buf);
         const int32_t *sc = CHEBFD_WC(buf);
 
         // slots of the row (entries past its width gather the row itself with
         // coefficient 0; when every chunk holds MAXW slots per row the selects fold away)
-        // (UNI: every row has exactly MAXW slots, no selects)
         int cc[MAXW];
         int wdt = MAXW, base = 0;
-        if (i < a.n) {
+        if (live) {
             const int cl = rr >> 5;
             base = (UNI ? cl * 32 * MAXW : CHEBFD_WCOFF(buf)[cl]) + (rr & 31);
             if constexpr (!UNI) wdt = CHEBFD_WCW(buf)[cl];
 #pragma unroll
             for (int k = 0; k < MAXW; ++k) {
                 const bool act = UNI || k < wdt;
-                cc[k] = act ? sc[base + k * 32] : static_cast<int>(i);
+                cc[k] = act ? sc[base + k * 32] : i;
             }
         }
         // gathers outside the window go to global memory (issued before the
         // prefetches, so waiting for them leaves the prefetches in flight)
         PK u[MAXW];
         bool inw[MAXW];
-        if (i < a.n) {
+        if (live) {
 #pragma unroll
             for (int k = 0; k < MAXW; ++k) {
                 inw[k] = static_cast<unsigned>(cc[k] - wlo) < static_cast<unsigned>((2 * kWinHalo + 1) * TR);
@@ -257,22 +276,25 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
         }
         // prefetches: next tile's matrix slots, W and Y rows; the block entering the window
         PK rf;
-        const int64_t nb_in = tile + kWinHalo + 1;
+        const int nb_in = tile + kWinHalo + 1;
         const bool ring_in = more && row_ok(nb_in);
-        if (ring_in) rf = load_pack<T, CPL, false>(P + 2 * ((nb_in * TR + rr) * NB + jc));
+        if (ring_in) rf = load_pack<T, CPL, false>(P + 2 * ((int64_t)(nb_in * TR + rr) * NB + jc));
         if (more) fetch_mat(tile + 1);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+            asm volatile("" ::"v"(held_w.re[c]), "v"(held_w.im[c]), "v"(held_y.re[c]), "v"(held_y.im[c]));
         // row streams of W and Y
+        const int64_t e = 2 * ((int64_t)i * NB + jc);
         PK o, yv;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) o.re[c] = o.im[c] = yv.re[c] = yv.im[c] = T(0);
-        if (i < a.n) {
-            const int64_t e = 2 * (i * NB + jc);
+        if (live) {
             if constexpr (!mode_first(MODE)) o = load_pack<T, CPL, true>(static_cast<const T *>(a.O) + e);
             if constexpr (MODE == kModeStep) yv = load_pack<T, CPL, true>(static_cast<const T *>(a.Y) + e);
         }
 
-        if (i < a.n) {
-            const int64_t e = 2 * (i * NB + jc);
+        if (live) {
+            PK nw, yo;
             const PK up = load_pack<T, CPL, false>(CHEBFD_RING(i));
 #pragma unroll
             for (int k = 0; k < MAXW; ++k)
@@ -294,7 +316,6 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
                     acc_im[c] = fma(h.y, u[k].re[c], acc_im[c]);
                 }
             }
-            PK nw;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const T hu_re = fma(alpha, acc_re[c], beta * up.re[c]);
@@ -307,29 +328,30 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
                     nw.im[c] = fma(T(2), hu_im, -o.im[c]);
                 }
             }
+            if constexpr (MODE == kModeSecond) {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    yo.re[c] = fma(g0, o.re[c], fma(g1, up.re[c], g2 * nw.re[c]));
+                    yo.im[c] = fma(g0, o.im[c], fma(g1, up.im[c], g2 * nw.im[c]));
+                }
+            } else if constexpr (MODE == kModeStep) {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    yo.re[c] = fma(g2, nw.re[c], yv.re[c]);
+                    yo.im[c] = fma(g2, nw.im[c], yv.im[c]);
+                }
+            }
             if constexpr (mode_first(MODE)) {
                 store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
             } else if constexpr (MODE == kModeSecond) {
                 store_pack_nt<T, CPL>(static_cast<T *>(a.N) + e, nw);
-                PK y;
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    y.re[c] = fma(g0, o.re[c], fma(g1, up.re[c], g2 * nw.re[c]));
-                    y.im[c] = fma(g0, o.im[c], fma(g1, up.im[c], g2 * nw.im[c]));
-                }
-                store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, y);  // Y aliases O: row i's entry is read only here
+                store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, yo);  // Y aliases O: row i's entry is read only here
             } else {
                 store_pack_nt<T, CPL>(static_cast<T *>(a.O) + e, nw);
-                if constexpr (MODE == kModeStep) {
-                    PK y;
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        y.re[c] = fma(g2, nw.re[c], yv.re[c]);
-                        y.im[c] = fma(g2, nw.im[c], yv.im[c]);
-                    }
-                    store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, y);
-                }
+                if constexpr (MODE == kModeStep) store_pack_nt<T, CPL>(static_cast<T *>(a.Y) + e, yo);
             }
+            held_w = nw;
+            if constexpr (MODE == kModeSecond || MODE == kModeStep) held_y = yo;
             if constexpr (mode_dots(MODE)) {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
@@ -341,12 +363,19 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
             }
         }
         // block tile + kWinHalo + 1 replaces block tile - kWinHalo - 1 (outside
-        // this tile's window); the next tile's slots go to the idle buffer
+        // this tile's window); the next tile's slots go to the idle buffer.  Their
+        // loads were issued before the W and Y loads and the stores, so the wait
+        // for them leaves those in flight; the stores also stay in flight across
+        // the barrier (it orders LDS only; no other row reads this row's W or Y).
         if (ring_in) ring_store(nb_in, rf);
         if (more) deposit_mat(tile + 1, buf ^ 1);
         __syncthreads();
         buf ^= 1;
-    }
+    };
+    // full tiles, then the ragged last tile of the matrix (if it is in this range)
+    const int te_full = te < n32 / TR ? te : (n32 / TR > tb ? n32 / TR : tb);
+    for (int tile = tb; tile < te_full; ++tile) tile_body(tile, std::true_type{});
+    for (int tile = te_full; tile < te; ++tile) tile_body(tile, std::false_type{});
 
     if constexpr (!mode_dots(MODE)) return;
     // workgroup reduction over the TR lanes of each column, fixed order;
@@ -432,12 +461,15 @@ bool set_win_attr() {
 bool win_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, WinGeometry *g) {
     if (H->C != 32 || H->max_width > kWinWidth) return false;
     int tr;
-    // instances where the window beats the LDS-staged kernel (measured); c64 with
-    // n_b = 32 is not among them: its step already runs near the stream rate
+    // instances where the window beats the LDS-staged kernel (measured): FP64
+    // n_b = 32, c64 n_b = 64, and c64 n_b = 32 on large matrices (tiles of 64
+    // rows; with few tiles per workgroup the LDS-staged kernel is faster there)
     if (prec == CHEBFD_PREC_FP64 && nb == 32)
         tr = WinShape<double, 32>::TR;
     else if (prec == CHEBFD_PREC_MIXED && nb == 64)
         tr = WinShape<float, 64>::TR;
+    else if (prec == CHEBFD_PREC_MIXED && nb == 32 && H->n >= (int64_t)kWinC64Nb32Tiles * num_cus * 64)
+        tr = WinShape<float, 32>::TR;
     else
         return false;
     const int local = H->window_local[tr == 32 ? 0 : 1];
@@ -452,7 +484,8 @@ bool win_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, WinGeom
     if (g->ntiles < 2 * G) return false;
     static bool attr_ok =
         set_win_attr<double, 32, kWinWidth, true>() && set_win_attr<double, 32, kWinWidth, false>() &&
-        set_win_attr<float, 64, kWinWidth, true>() && set_win_attr<float, 64, kWinWidth, false>();
+        set_win_attr<float, 64, kWinWidth, true>() && set_win_attr<float, 64, kWinWidth, false>() &&
+        set_win_attr<float, 32, kWinWidth, true>() && set_win_attr<float, 32, kWinWidth, false>();
     if (!attr_ok) return false;
     g->G = static_cast<int>(G);
     return true;
@@ -461,6 +494,7 @@ bool win_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, WinGeom
 int launch_win_step(int prec, int nb, int mode, const StepArgs &a, const WinGeometry &g, hipStream_t s) {
     if (prec == CHEBFD_PREC_FP64 && nb == 32) return launch_win_w<double, 32>(mode, a, g, s);
     if (prec == CHEBFD_PREC_MIXED && nb == 64) return launch_win_w<float, 64>(mode, a, g, s);
+    if (prec == CHEBFD_PREC_MIXED && nb == 32) return launch_win_w<float, 32>(mode, a, g, s);
     CHEBFD_FAIL(CHEBFD_EINVAL, "window kernel has no instance for prec %d, n_b = %d", prec, nb);
 }
 

@@ -69,6 +69,7 @@ constexpr int kWinBlocks = 8;
 constexpr int kWinHalo = 3;
 constexpr int kWinWidth = 13;       // rows of at most this many stored entries
 constexpr int kWinMinLocal = 700;
+constexpr int kWinC64Nb32Tiles = 256;   // c64 n_b = 32 takes the window kernel from this many 64-row tiles per CU
 struct WinGeometry {
     int tr;             // rows per tile
     int uniform;        // 1: every chunk holds exactly kWinWidth slots per row

@@ -43,6 +43,26 @@ def _split(dims, parts):
     return tuple(split)
 
 
+def pencil_groups(npx: int, npy: int, sweeps: int):
+    """Shape (gx, gy), gx gy = sweeps, of the block of pencils that the sweep ranges of
+    one box take at the same time, or None when no such block tiles the npx x npy
+    pencils.  A gather that leaves its pencil in x or y finds its row in L2 when the
+    neighbour pencil is in the same block; the faces on the block's edge miss, a
+    share of 1 / gx of the x faces and 1 / gy of the y faces: the shape minimising
+    1 / gx + 1 / gy (wider in x on ties) is taken."""
+    best = None
+    for gx in range(1, sweeps + 1):
+        if sweeps % gx:
+            continue
+        gy = sweeps // gx
+        if npx % gx or npy % gy:
+            continue
+        cost = 1.0 / gx + 1.0 / gy
+        if best is None or cost < best[0] - 1e-12 or (abs(cost - best[0]) <= 1e-12 and gx > best[1]):
+            best = (cost, gx, gy)
+    return None if best is None else (best[1], best[2])
+
+
 def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int = 8, slab: int = 8,
                       pencil=(4, 4), sweeps: int = 32):
     """Row order (int32 permutation of 0..n-1, order[k] = original row placed k-th) for a
@@ -57,11 +77,13 @@ def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int =
 
     ``sweeps``: the window step kernel splits each box's rows into this many
     contiguous ranges, swept side by side by the workgroups of one XCD (32 CUs
-    per XCD).  When it divides the number of pencils of a box, pencil p is put
-    into range p % sweeps (at position p // sweeps), so the pencils next to p in
-    x and y are swept at the same time by other workgroups of the same XCD and
+    per XCD).  When it divides the number of pencils of a box, the ranges take
+    a block of gx x gy pencils at a time (``pencil_groups``; 8 x 4 for 32
+    ranges where the box allows it): the pencils next to a pencil in x and y are
+    then mostly swept at the same time by other workgroups of the same XCD, and
     the gathers that leave a workgroup's LDS window find their rows in L2.
-    ``sweeps=1`` keeps the pencils in x-fastest order."""
+    When no block shape fits, pencil p goes to range p % sweeps (position
+    p // sweeps).  ``sweeps=1`` keeps the pencils in x-fastest order."""
     dims = (int(Nx), int(Ny), int(Nz))
     split = None
     while parts >= 1 and split is None:
@@ -82,8 +104,18 @@ def lattice_row_order(Nx: int, Ny: int, Nz: int, orbitals: int = 4, parts: int =
         px, py = pencil
         lx = x % bx
         npx, npen = bx // px, (bx // px) * (by // py)
-        pen = lx // px + npx * (ly // py)                   # pencil index in the box, x fastest
-        if sweeps > 1 and npen % sweeps == 0:
+        ipx, ipy = lx // px, ly // py                      # pencil coordinates in the box
+        npy = by // py
+        pen = ipx + npx * ipy                               # pencil index in the box, x fastest
+        grp = pencil_groups(npx, npy, sweeps) if sweeps > 1 and npen % sweeps == 0 else None
+        if grp is not None:
+            # the sweeps side by side take a gx x gy block of pencils at a time: range
+            # r = (ipx % gx) + gx (ipy % gy), position = block index (x fastest)
+            gx, gy = grp
+            r = ipx % gx + gx * (ipy % gy)
+            blk = ipx // gx + (npx // gx) * (ipy // gy)
+            pen = r * (npen // sweeps) + blk
+        elif sweeps > 1 and npen % sweeps == 0:
             pen = (pen % sweeps) * (npen // sweeps) + pen // sweeps
         key = np.lexsort((lx % px, ly % py, z % bz, pen, box))
     else:

@@ -58,15 +58,16 @@ def _widened(lo, hi):
     return lo2, hi2, s
 
 
-# prec, n_b, kernel the library must pick for the benchmark's 64x64x32 matrix
-FULL_CASES = [(0, 32, "window"), (1, 64, "window"), (1, 32, "lds")]
+# lattice, prec, n_b, n_p, kernel the library must pick (the benchmark's 64x64x32 matrix; c64
+# n_b = 32 on the 128x128x64 lattice, where it takes the window kernel)
+FULL_CASES = [((64, 64, 32), 0, 32, 60, "window"), ((64, 64, 32), 1, 64, 60, "window"),
+              ((64, 64, 32), 1, 32, 60, "lds"), ((128, 128, 64), 1, 32, 20, "window")]
 
 
-@pytest.mark.parametrize("prec,n_b,kernel", FULL_CASES)
-def test_full_size_filter_matches_oracle(P, prec, n_b, kernel):
+@pytest.mark.parametrize("dims,prec,n_b,n_p,kernel", FULL_CASES)
+def test_full_size_filter_matches_oracle(P, dims, prec, n_b, n_p, kernel):
     from paper_1803_02156_amd.ordering import lattice_row_order
-    print(f"\n# full-size oracle parity: 64x64x32 lattice order, prec {prec}, n_b {n_b}", flush=True)
-    dims, n_p = (64, 64, 32), 60
+    print(f"\n# full-size oracle parity: {dims} lattice order, prec {prec}, n_b {n_b}", flush=True)
     H = topi_csr(*dims, m=1.0, W=1.0, seed=1002)
     n = len(H[0]) - 1
     M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=prec, order=lattice_row_order(*dims))
@@ -117,8 +118,10 @@ def _plane_wave(dims, j, v):
 
 BLOCH_CASES = [
     ((128, 128, 64), 0, 32, "window"),
+    ((128, 128, 64), 1, 32, "window"),     # c64 n_b = 32 takes the window kernel from 128x128x64 on
     ((256, 256, 128), 0, 32, "window"),    # the largest single-GPU configuration, benchmark geometry
-    ((256, 256, 128), 1, 32, "lds"),
+    ((256, 256, 128), 1, 32, "window"),
+    ((256, 256, 128), 1, 64, "window"),
 ]
 
 

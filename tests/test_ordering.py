@@ -75,3 +75,44 @@ def test_pencils_interleaved_over_sweeps():
             far = (a // box_rows == b // box_rows) & (np.abs(a - b) > 96)   # same box, outside the window
             close = np.mean(np.abs(a[far] % span - b[far] % span) <= 64)
             assert lo <= close <= hi, (sweeps, close)
+
+
+def test_pencil_groups_shape():
+    from paper_1803_02156_amd.ordering import pencil_groups
+    assert pencil_groups(16, 32, 32) == (8, 4)
+    assert pencil_groups(8, 16, 32) == (8, 4)
+    assert pencil_groups(4, 8, 32) == (4, 8)
+    assert pencil_groups(32, 1, 32) == (32, 1)
+    assert pencil_groups(3, 5, 32) is None
+
+
+def test_grouped_sweeps_take_neighbour_pencils_together():
+    """Boxes of 16 x 16 pencils: the 32 ranges take 8 x 4 pencil blocks at a time,
+    so fewer x/y neighbours outside the LDS window are swept at another time than
+    with the plain deal (32 pencils of two pencil rows)."""
+    import paper_1803_02156_amd.ordering as O
+    Nx, Ny, Nz = 128, 256, 32
+    s = np.arange(Nx * Ny * Nz)
+    x, y, z = s % Nx, (s // Nx) % Ny, s // (Nx * Ny)
+    nbrs = ((x + 1) % Nx + Nx * (y + Ny * z), x + Nx * ((y + 1) % Ny + Ny * z))
+
+    def not_together(o):
+        n_rows = o.size
+        box_rows, span = n_rows // 8, n_rows // (8 * 32)
+        pos = np.empty(o.size, dtype=np.int64)
+        pos[o] = np.arange(o.size)
+        out = 0.0
+        for nb in nbrs:
+            a, b = pos[4 * s], pos[4 * nb]
+            far = np.abs(a - b) > 96
+            together = (a // box_rows == b // box_rows) & (np.abs(a % span - b % span) <= 64)
+            out += np.mean(far & ~together)
+        return out
+    grouped = not_together(O.lattice_row_order(Nx, Ny, Nz))
+    saved = O.pencil_groups
+    try:
+        O.pencil_groups = lambda *a: None
+        plain = not_together(O.lattice_row_order(Nx, Ny, Nz))
+    finally:
+        O.pencil_groups = saved
+    assert grouped < 0.75 * plain, (grouped, plain)
