@@ -3,7 +3,7 @@
 Plain FP64 ChebFD following the paper (Kreutzer et al., arXiv:1803.02156):
 the polynomial filter of Sect. 2, Alg. 1 applied blockwise as in Sect. 3.3,
 Alg. 2, followed by the orthogonalisation and restart that Sect. 2 names
-(SVQB) and a Rayleigh-Ritz projection.  The paper defers the window function,
+(SVQB, or TSQR as the alternative) and a Rayleigh-Ritz projection.  The paper defers the window function,
 the damping, the restart details and the convergence test to other work;
 the readings used for those are stated at each function.
 
@@ -23,7 +23,8 @@ from . import build as _build
 __all__ = [
     "load_library", "gershgorin_bounds", "scale_factors", "window_coefficients",
     "jackson_damping", "filter_coefficients", "spmmv", "chebyshev_filter",
-    "kpm_moments", "count_estimate", "choose_params", "svqb", "rayleigh_ritz", "residual_norms",
+    "kpm_moments", "count_estimate", "choose_params", "svqb", "qr_positive", "qr_orth",
+    "rayleigh_ritz", "residual_norms",
     "fix_phases", "chebfd_solve", "SolveResult",
 ]
 
@@ -266,6 +267,41 @@ def svqb(Y: np.ndarray, tau: float | None = None):
     return Q, int(np.count_nonzero(~keep))
 
 
+def qr_positive(X: np.ndarray):
+    """X = Q R with orthonormal columns in Q and R upper triangular with a real,
+    non-negative diagonal: the factorisation TSQR computes (Sect. 2 names TSQR
+    as the alternative to SVQB before the restart).  For X of full column rank
+    it is unique, so every stable algorithm -- a Householder QR here (LAPACK as a
+    library primitive), a reduction tree of Householder QRs on the device --
+    reaches the same Q and R up to rounding.  Returns (Q, R)."""
+    Q, R = np.linalg.qr(X, mode="reduced")
+    d = np.diag(R).copy()
+    a = np.abs(d)
+    ph = np.ones_like(d)
+    ph[a > 0] = d[a > 0] / a[a > 0]
+    return Q * ph[None, :], R * ph.conj()[:, None]
+
+
+def qr_orth(Y: np.ndarray, tau: float | None = None):
+    """Rank-revealing orthogonalisation by QR (the TSQR alternative of Sect. 2).
+
+    Y = Q R (qr_positive); column k of Y depends on the columns before it when
+    |R_kk|^2 <= tau ||y_k||^2 (its distance to their span is at the level the
+    data resolves), and its direction q_k carries no information.  Such
+    columns are removed from Y and the rest factorised again, so that no kept
+    column was orthogonalised against a direction made of rounding errors.
+    tau as in svqb (the same squared relative singular value floor).  Returns
+    (Q of the kept columns in their order, n_dropped)."""
+    if tau is None:
+        tau = max(100.0 * 2.0 ** -53, (10.0 * 2.0 ** -53) ** 2)
+    Q, R = qr_positive(Y)
+    col2 = np.sum(np.abs(Y) ** 2, axis=0)
+    keep = np.abs(np.diag(R)) ** 2 > tau * col2
+    if np.all(keep):
+        return Q, 0
+    return qr_positive(Y[:, keep])[0], int(np.count_nonzero(~keep))
+
+
 def rayleigh_ritz(H, Q: np.ndarray):
     """Ritz values (ascending) and vectors of H on span(Q), Q orthonormal.
 
@@ -304,11 +340,12 @@ class SolveResult:
 
 def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
                  X0: np.ndarray, tol: float = 1e-9, max_iter: int = 50,
-                 refill_seed: int = 0, bounds=None, trace=None):
+                 refill_seed: int = 0, bounds=None, trace=None, orth: str = "svqb"):
     """Eigenpairs of the Hermitian CSR matrix H with eigenvalues in [lam_L, lam_R].
 
     Each iteration: filter the block (Alg. 2 / Alg. 1), orthonormalise it by
-    SVQB applied twice (rank revealing), Rayleigh-Ritz on the kept directions,
+    SVQB applied twice (orth="svqb") or by one rank-revealing QR (orth="tsqr",
+    qr_orth), both rank revealing, Rayleigh-Ritz on the kept directions,
     restart from those Ritz vectors plus fresh random-phase vectors in place of
     the dropped directions (so that unfiltered vectors never enter a
     Rayleigh-Ritz step).
@@ -336,6 +373,8 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
     """
     from topi import random_phase_block
 
+    if orth not in ("svqb", "tsqr"):
+        raise ValueError(f"orth must be 'svqb' or 'tsqr', not {orth!r}")
     lo, hi = gershgorin_bounds(H) if bounds is None else bounds
     alpha, beta = scale_factors(lo, hi)
     gamma = filter_coefficients(lam_L, lam_R, alpha, beta, n_p)
@@ -353,9 +392,12 @@ def chebfd_solve(H, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
         if it == 1:
             mu = kpm_moments(eta, nu)
             count_est = count_estimate(mu, n, alpha * lam_L + beta, alpha * lam_R + beta)
-        Q, d1 = svqb(Y)
-        Q, d2 = svqb(Q)
-        dropped = d1 + d2
+        if orth == "tsqr":
+            Q, dropped = qr_orth(Y)
+        else:
+            Q, d1 = svqb(Y)
+            Q, d2 = svqb(Q)
+            dropped = d1 + d2
         theta, Z = rayleigh_ritz(H, Q)
         res = residual_norms(H, Z, theta)
         if trace is not None:

@@ -211,6 +211,65 @@ def test_svqb_drops_dependent_columns():
     assert np.max(np.abs(Y - Q @ (Q.conj().T @ Y))) < 1e-10
 
 
+def _dft_columns(n, m):
+    """m columns of the unitary n-point DFT matrix: orthonormal by construction."""
+    j = np.arange(n)[:, None]
+    k = np.arange(m)[None, :]
+    return np.exp(-2j * np.pi * j * k / n) / np.sqrt(n)
+
+
+def test_qr_positive_recovers_known_factors():
+    # X = V U with V orthonormal and U upper triangular with a positive diagonal:
+    # by uniqueness of that factorisation Q = V and R = U
+    rng = np.random.default_rng(7)
+    n, m = 96, 11
+    V = _dft_columns(n, m)[:, rng.permutation(m)]
+    U = np.triu(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)), 1)
+    U += np.diag(rng.uniform(0.5, 3.0, m))
+    Q, R = O.qr_positive(V @ U)
+    assert np.max(np.abs(Q - V)) < 1e-13
+    assert np.max(np.abs(R - U)) < 1e-13
+
+
+def test_qr_positive_matches_modified_gram_schmidt():
+    # an independent algorithm, element by element in plain loops
+    rng = np.random.default_rng(8)
+    n, m = 14, 5
+    X = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+    Qg = [[0j] * m for _ in range(n)]
+    Rg = [[0j] * m for _ in range(m)]
+    W = [[complex(X[i, j]) for j in range(m)] for i in range(n)]
+    for k in range(m):
+        nrm = sum(abs(W[i][k]) ** 2 for i in range(n)) ** 0.5
+        Rg[k][k] = nrm
+        for i in range(n):
+            Qg[i][k] = W[i][k] / nrm
+        for j in range(k + 1, m):
+            r = sum(Qg[i][k].conjugate() * W[i][j] for i in range(n))
+            Rg[k][j] = r
+            for i in range(n):
+                W[i][j] -= r * Qg[i][k]
+    Q, R = O.qr_positive(X)
+    assert np.max(np.abs(Q - np.array(Qg))) < 1e-13
+    assert np.max(np.abs(R - np.array(Rg))) < 1e-13
+    assert np.all(np.diag(R).imag == 0) and np.all(np.diag(R).real > 0)
+
+
+def test_qr_orth_drops_dependent_columns():
+    rng = np.random.default_rng(9)
+    Y = rng.standard_normal((300, 8)) + 1j * rng.standard_normal((300, 8))
+    Y[:, 3] = Y[:, 1] * (0.5 - 2j)
+    Y[:, 6] = 2 * Y[:, 0] - Y[:, 2]
+    Y[:, 5] *= 1e-5          # small but independent: kept
+    Q, nd = O.qr_orth(Y)
+    assert nd == 2 and Q.shape == (300, 6)
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(6))) < 1e-13
+    assert np.max(np.abs(Y - Q @ (Q.conj().T @ Y))) < 1e-10
+    # the kept directions are the QR of the independent columns, in order
+    Qi, _ = O.qr_positive(Y[:, [0, 1, 2, 4, 5, 7]])
+    assert np.max(np.abs(Q - Qi)) < 1e-12
+
+
 def test_rayleigh_ritz_on_exact_invariant_subspace():
     H = topi_csr(4, 3, 3, m=1.0, W=2.0, seed=12)
     A = csr_to_dense(*H)
@@ -247,7 +306,8 @@ def test_fix_phases():
     ((4, 4, 3), 2.0, (-0.8, 0.8), 32, 150, 16),
     ((6, 6, 4), 1.0, (-0.35, 0.35), 32, 200, 32),
 ])
-def test_solve_matches_lapack(dims, W, interval, n_s, n_p, n_b):
+@pytest.mark.parametrize("orth", ["svqb", "tsqr"])
+def test_solve_matches_lapack(dims, W, interval, n_s, n_p, n_b, orth):
     H = topi_csr(*dims, m=1.0, W=W, seed=1001)
     A = csr_to_dense(*H)
     n = A.shape[0]
@@ -255,7 +315,7 @@ def test_solve_matches_lapack(dims, W, interval, n_s, n_p, n_b):
     lam_L, lam_R = interval
     ref = e[(e >= lam_L) & (e <= lam_R)]
     res = O.chebfd_solve(H, lam_L, lam_R, n_s, n_p, n_b, random_phase_block(n, n_s, 43),
-                         refill_seed=44)
+                         refill_seed=44, orth=orth)
     assert res.status == 0
     assert res.n_found == len(ref) and len(ref) % 2 == 0
     assert np.max(np.abs(np.sort(res.theta[:res.n_found]) - ref)) < 1e-12
