@@ -184,8 +184,9 @@ def interval_for_count(P, M, target, seed=7, n_steps=1024, R=16):
 def time_to_converged(P, lattice, W, n_b, target):
     """Full ChebFD runs (filter, SVQB, Rayleigh-Ritz, residuals, restarts) on one
     matrix and interval: FP64 and mixed precision with the heuristic's (n_p, n_s)
-    (the fallback rule), and mixed precision with the learned (n_p, n_s).  Wall
-    time from the first launch to the synchronised end; matrix build excluded."""
+    (the fallback rule), mixed precision with the learned (n_p, n_s), and mixed
+    precision with the heuristic's choice and TSQR in place of SVQB.  Wall time
+    from the first launch to the synchronised end; matrix build excluded."""
     import torch
     from paper_1803_02156_amd import predictor as PR
     from paper_1803_02156_amd.ordering import lattice_row_order
@@ -205,18 +206,20 @@ def time_to_converged(P, lattice, W, n_b, target):
            "interval": [-delta, delta], "count_est_kpm": cnt, "count_est_features": cnt_f,
            "heuristic": {"n_p": hp, "n_s": hs, "kappa": pred["kappa"]}, "learned": {"n_p": lp, "n_s": ls}}
     runs = {}
-    for name, M, n_p, n_s in (("fp64_heuristic", M64, hp, hs), ("mixed_heuristic", M32, hp, hs),
-                              ("mixed_learned", M32, lp, ls)):
+    for name, M, n_p, n_s, orth in (("fp64_heuristic", M64, hp, hs, "svqb"), ("mixed_heuristic", M32, hp, hs, "svqb"),
+                                    ("mixed_learned", M32, lp, ls, "svqb"),
+                                    ("mixed_heuristic_tsqr", M32, hp, hs, "tsqr")):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = P.chebfd_solve(M, M64, -delta, delta, n_s, n_p, n_b, seed=43, max_iter=12, want_vectors=False)
+        r = P.chebfd_solve(M, M64, -delta, delta, n_s, n_p, n_b, seed=43, max_iter=12, want_vectors=False,
+                           orth=orth)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         nf, st = r.n_found, r.stats
         runs[name] = r
         out[name] = {
             "seconds": round(dt, 3), "status": r.status, "iterations": st.iterations, "n_found": nf,
-            "n_p": n_p, "n_s": n_s, "max_resid": float(np.max(r.resid[:nf])) if nf else None,
+            "n_p": n_p, "n_s": n_s, "orth": orth, "max_resid": float(np.max(r.resid[:nf])) if nf else None,
             "tol": 1e-9 if M is M64 else 1e-7,
             "t_filter": round(st.t_filter, 3), "t_orth": round(st.t_orth, 3), "t_rr": round(st.t_rr, 3),
             "t_resid": round(st.t_resid, 3),
@@ -225,7 +228,7 @@ def time_to_converged(P, lattice, W, n_b, target):
         log(f"solve {name} (n_p {n_p}, n_s {n_s}): {dt:.2f} s, status {r.status}, {st.iterations} iterations, "
             f"{nf} pairs")
     ref = runs["fp64_heuristic"]
-    for name in ("mixed_heuristic", "mixed_learned"):
+    for name in ("mixed_heuristic", "mixed_learned", "mixed_heuristic_tsqr"):
         r = runs[name]
         o = out[name]
         o["all_pairs_of_fp64_run"] = bool(r.status == 0 and ref.status == 0 and r.n_found >= ref.n_found > 0)
@@ -487,6 +490,19 @@ def main():
                     "frac_of_fp64_mfma_peak": round(useful / (gram_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
                     "flops_counted": "8 n n_s (n_s + 1) / 2: the distinct entries of the Hermitian S"}
             log(f"gram: {gram_ms:.1f} ms, {gram['tflops']} TFLOP/s")
+            # TSQR of the same search space (the alternative orthogonalisation): panels of
+            # min(n_b, 32) columns, block Gram-Schmidt twice + a Householder tree per panel
+            P.chebfd_tsqr(Y)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            P.chebfd_tsqr(Y)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tsqr_ms = e0.elapsed_time(e1)
+            gram["tsqr_ms"] = round(tsqr_ms, 3)
+            gram["tsqr_note"] = ("chebfd_tsqr of the same c64 block (Q c64, R FP64); one TSQR replaces "
+                                 "the two SVQB steps of an iteration (each a Gram, a small eigensolve, an update)")
+            log(f"tsqr: {tsqr_ms:.1f} ms")
             del Y
         del M32
         torch.cuda.empty_cache()

@@ -323,6 +323,25 @@ int chebfd_update(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec_a
                   const double *d_m, int32_t ldm, int32_t prec_z, void *d_z, void *stream);
 
 /*
+ * Tall-skinny QR (TSQR; Sect. 2 names it as the alternative to SVQB in the
+ * orthogonalisation before the restart): d_y = Q R for an n x m block vector
+ * d_y in the blocked layout (block width n_b, precision prec), 1 <= m <= n,
+ * m <= 4096.  Q (n x m, same layout and precision) is written to d_q, which
+ * must not overlap d_y; R (m x m, FP64 complex, column-major, ld_r >= m) to
+ * d_r: upper triangular with a real non-negative diagonal (the unique such
+ * factorisation when d_y has full column rank; for a dependent column k,
+ * R_kk is at rounding level and column k of Q is an unspecified unit vector).
+ * Columns are taken in panels of min(n_b, 32): each panel is projected
+ * against the finished ones twice (block Gram-Schmidt with FP64 MFMA), then
+ * factorised by a reduction tree of Householder QRs over 256-row blocks.  All
+ * arithmetic is FP64.  d_work: chebfd_tsqr_query bytes, 256-byte aligned.
+ * Asynchronous on `stream`.
+ */
+int chebfd_tsqr_query(int64_t n, int32_t m, int32_t n_b, size_t *work_bytes);
+int chebfd_tsqr(int64_t n, int32_t m, int32_t n_b, int32_t prec, const void *d_y, void *d_q, double *d_r,
+                int32_t ld_r, void *d_work, size_t work_bytes, void *stream);
+
+/*
  * Eigendecomposition of a Hermitian m x m FP64 complex matrix (m <= 512) by
  * cyclic Jacobi rotations (one launch per round of disjoint rotations, one
  * workgroup per rotation pair): d_w receives the eigenvalues in
@@ -335,11 +354,14 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
                 void *d_work, size_t work_bytes, void *stream, int32_t *h_sweeps);
 
 /*
- * The ChebFD iteration (Sect. 2): filter the search block, orthonormalise it by
- * SVQB twice (rank revealing: Gram eigenvalues below
- * max(100 eps, (10 eps_store)^2) times the largest are dropped), Rayleigh-Ritz on
- * the kept directions, residuals in FP64, restart from the Ritz vectors plus
- * fresh random-phase vectors in place of dropped directions.
+ * The ChebFD iteration (Sect. 2): filter the search block, orthonormalise it
+ * (rank revealing, tau = max(100 eps, (10 eps_store)^2)) by SVQB twice
+ * (p->orth CHEBFD_ORTH_SVQB: Gram eigenvalues below tau times the largest are
+ * dropped) or by TSQR (CHEBFD_ORTH_TSQR: chebfd_tsqr; a column k with
+ * |R_kk|^2 <= tau ||y_k||^2 is dropped and the kept columns are factorised
+ * again), Rayleigh-Ritz on the kept directions, residuals in FP64, restart
+ * from the Ritz vectors plus fresh random-phase vectors in place of dropped
+ * directions.
  * A Ritz pair inside the closed interval [lam_L, lam_R] is converged if its
  * residual ||H z - theta z|| (||z|| = 1) is <= tol, unresolved otherwise; the
  * iteration stops when the number of converged pairs repeats the previous
@@ -370,13 +392,16 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
  * NULL): the Ritz vectors in the same order, each scaled so that its largest
  * entry is real positive; columns beyond the kept directions are zero.
  */
+#define CHEBFD_ORTH_SVQB 0
+#define CHEBFD_ORTH_TSQR 1
+
 typedef struct chebfd_params {
     double lam_L, lam_R;   /* closed search interval, H's units */
     int32_t n_s, n_p, n_b; /* subspace size (multiple of n_b), filter degree, block width */
     int32_t prec;          /* CHEBFD_PREC_* of the filter */
     double tol;            /* residual tolerance */
     int32_t max_iter;
-    int32_t reserved;
+    int32_t orth;          /* CHEBFD_ORTH_SVQB (0) or CHEBFD_ORTH_TSQR (1) */
     uint64_t seed;
     double spec_lo, spec_hi; /* spectral bounds of H; NaN for Gershgorin bounds */
 } chebfd_params;

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libchebfd.so")
 OK, NOT_CONVERGED, SUBSPACE_SMALL = 0, 1, 2
 EINVAL, EHIP, EWORKSPACE, EINTERVAL, ENUMERIC = -1, -2, -3, -4, -5
 PREC_FP64, PREC_MIXED = 0, 1
+ORTH_SVQB, ORTH_TSQR = 0, 1
 FEATURE_R, FEATURE_MOMENTS = 16, 256
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 258, 128, 2, 49922
 NP_MIN, NP_MAX = 50, 20000
@@ -31,7 +32,7 @@ class ChebfdMatrix(ctypes.Structure):
 class ChebfdParams(ctypes.Structure):
     _fields_ = [
         ("lam_L", f64), ("lam_R", f64), ("n_s", i32), ("n_p", i32), ("n_b", i32), ("prec", i32),
-        ("tol", f64), ("max_iter", i32), ("reserved", i32), ("seed", ctypes.c_uint64),
+        ("tol", f64), ("max_iter", i32), ("orth", i32), ("seed", ctypes.c_uint64),
         ("spec_lo", f64), ("spec_hi", f64),
     ]
 
@@ -81,6 +82,8 @@ SIGNATURES = {
     "chebfd_gram_query": (ctypes.c_int, [i64, i32, i32, ctypes.POINTER(sz)]),
     "chebfd_gram": (ctypes.c_int, [i64, i32, i32, i32, i32, P, P, P, i32, P, sz, P]),
     "chebfd_update": (ctypes.c_int, [i64, i32, i32, i32, i32, P, P, i32, i32, P, P]),
+    "chebfd_tsqr_query": (ctypes.c_int, [i64, i32, i32, ctypes.POINTER(sz)]),
+    "chebfd_tsqr": (ctypes.c_int, [i64, i32, i32, i32, P, P, P, i32, P, sz, P]),
     "chebfd_heev_query": (ctypes.c_int, [i32, ctypes.POINTER(sz)]),
     "chebfd_heev": (ctypes.c_int, [i32, P, i32, P, i32, P, P, sz, P, ctypes.POINTER(i32)]),
     "chebfd_solve_query": (ctypes.c_int, [MP, MP, PP, ctypes.POINTER(sz)]),

@@ -12,7 +12,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchebfd.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["api.cpp", "filter.hip", "filter_rows.hip", "layout.hip", "dense.hip", "filter_lds.hip", "filter_win.hip", "blas1.hip", "stream.cpp", "solve.cpp", "mlp.hip", "predict.cpp"]
+SOURCES = ["api.cpp", "filter.hip", "filter_rows.hip", "layout.hip", "dense.hip", "filter_lds.hip", "filter_win.hip", "blas1.hip", "tsqr.hip", "stream.cpp", "solve.cpp", "mlp.hip", "predict.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

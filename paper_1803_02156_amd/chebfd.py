@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import PREC_FP64, PREC_MIXED, ChebfdError, check, load  # noqa: F401
+from ._abi import ORTH_SVQB, ORTH_TSQR, PREC_FP64, PREC_MIXED, ChebfdError, check, load  # noqa: F401
 
 _ALIGN = 256
 
@@ -324,6 +324,22 @@ def chebfd_update(a: torch.Tensor, M: torch.Tensor, prec_z: int | None = None):
     return z
 
 
+def chebfd_tsqr(y: torch.Tensor, m: int | None = None):
+    """Q, R with y = Q R (TSQR) for a blocked tensor y (n_blocks, n, n_b) holding m columns:
+    Q of the same shape and precision, R an (m, m) complex128 upper triangle with a real
+    non-negative diagonal."""
+    nblk, n, n_b = y.shape
+    m = nblk * n_b if m is None else m
+    prec = PREC_FP64 if y.dtype == torch.complex128 else PREC_MIXED
+    sz = ctypes.c_size_t()
+    check(load().chebfd_tsqr_query(n, m, n_b, ctypes.byref(sz)))
+    work = device_buffer(sz.value, y.device)
+    q = torch.zeros_like(y)
+    R = torch.zeros((m, m), dtype=torch.complex128, device=y.device)   # column-major m x m
+    check(load().chebfd_tsqr(n, m, n_b, prec, _ptr(y), _ptr(q), _ptr(R), m, _ptr(work), sz.value, _stream()))
+    return q, R.T
+
+
 def chebfd_heev(A: torch.Tensor):
     """Eigenvalues (ascending) and eigenvectors of a Hermitian complex128 CUDA matrix."""
     m = A.shape[0]
@@ -350,14 +366,16 @@ class SolveResult:
 
 def chebfd_solve(H: Matrix, H64: Matrix, lam_L: float, lam_R: float, n_s: int, n_p: int, n_b: int,
                  tol: float | None = None, max_iter: int = 50, seed: int = 0, x0: torch.Tensor | None = None,
-                 spec_bounds=None, want_vectors: bool = True):
-    """Run the device ChebFD iteration; returns theta, residuals, Ritz vectors (column-major c128)."""
+                 spec_bounds=None, want_vectors: bool = True, orth: str = "svqb"):
+    """Run the device ChebFD iteration; returns theta, residuals, Ritz vectors (column-major c128).
+    orth: "svqb" (SVQB twice) or "tsqr" (rank-revealing TSQR) before each Rayleigh-Ritz step."""
     prec = H.prec
     if tol is None:
         tol = 1e-9 if prec == PREC_FP64 else 1e-7
     p = _abi.ChebfdParams()
     p.lam_L, p.lam_R, p.n_s, p.n_p, p.n_b, p.prec = lam_L, lam_R, n_s, n_p, n_b, prec
     p.tol, p.max_iter, p.seed = tol, max_iter, seed
+    p.orth = {"svqb": ORTH_SVQB, "tsqr": ORTH_TSQR}[orth]
     p.spec_lo, p.spec_hi = (float("nan"), float("nan")) if spec_bounds is None else spec_bounds
     sz = ctypes.c_size_t()
     check(load().chebfd_solve_query(H.ref(), H64.ref(), ctypes.byref(p), ctypes.byref(sz)))

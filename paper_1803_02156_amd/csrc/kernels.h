@@ -102,6 +102,15 @@ int step_grid(int prec, int nb, int64_t npass, int num_cus);
 int launch_gram(const void *A, int prec_a, int nb_a, const void *B, int prec_b, int nb_b, int64_t n,
                 int m1, int m2, double *part, int nsplit, double *S, int ld, hipStream_t s);
 size_t gram_part_bytes(int m1, int m2, int nsplit);
+// Row splits of a Gram product S = A^H B (m1 x m2): enough workgroups for a few
+// full waves of the device (about 4096 64 x 64 tile-splits; the Hermitian
+// product forms about half of them) but at least 256 rows per split.
+inline int gram_splits(int64_t n, int m1, int m2) {
+    const int64_t tiles = (int64_t)((m1 + 63) / 64) * ((m2 + 63) / 64);
+    const int64_t want = (4096 + tiles - 1) / tiles;
+    const int64_t cap = n / 256 > 1 ? n / 256 : 1;
+    return static_cast<int>(want < 1024 ? (want < cap ? want : cap) : (1024 < cap ? 1024 : cap));
+}
 int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm, void *Z, int prec_z,
                   int nb_z, int64_t n, int m1, int m2, hipStream_t s);
 // Jacobi eigensolver (host-driven sweeps, one launch per round); synchronises `s`
@@ -124,6 +133,25 @@ int launch_random_phase(void *X, int prec, int64_t n, int nb, int c_begin, int c
 int launch_permute_columns(int rows, int m, const double *S, int lds, const int *order, double *T,
                            int ldt, hipStream_t s);
 int launch_fix_phases(void *Z, int prec, int64_t n, int nb, int m, double *phase, hipStream_t s);
+
+// TSQR (tsqr.hip): Y (n x m, blocked width nb, prec_y) = Q R, Q into a second
+// block vector (prec_q, same nb), R (m x m, FP64 complex, column-major, ldr)
+// upper triangular with a real non-negative diagonal.  Panels of
+// tsqr_panel_width(nb) columns; work buffers: T and U (n x panel width FP64
+// complex each), tree (tsqr_tree_bytes), C1 and C2 (m x panel width, leading
+// dimension ldc >= m) and gpart (tsqr_gpart_bytes).
+struct TsqrWork {
+    double *T, *U, *tree, *C1, *C2;
+    int ldc;
+    double *gpart;
+};
+int tsqr_panel_width(int nb);
+size_t tsqr_tree_bytes(int64_t n, int pw);
+size_t tsqr_gpart_bytes(int64_t n, int m, int nb);
+int tsqr_blocked(int64_t n, int m, int nb, int prec_y, const void *Y, int prec_q, void *Q, double *R, int ldr,
+                 const TsqrWork &w, hipStream_t s);
+// info[2k] = |R_kk|^2, info[2k + 1] = squared norm of column k of R
+int launch_tsqr_colinfo(int m, const double *R, int ldr, double *info, hipStream_t s);
 
 // layout / misc kernels (layout.hip)
 int launch_pack(const int32_t *perm, int64_t n, int m, int nb, int prec, const void *src,

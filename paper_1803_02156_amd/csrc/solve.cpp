@@ -31,19 +31,10 @@ size_t al(size_t v) { return round_up(v, 256); }
 // tolerance independent of m would never be met.
 double jacobi_tol(int m) { return 4.0 * std::max(m, 1) * 0x1.0p-53; }
 
-// Row splits of a Gram product S = A^H B (m1 x m2): enough workgroups for a few
-// full waves of the device (about 4096 64 x 64 tile-splits; the Hermitian
-// product forms about half of them) but at least 256 rows per split.
-int gram_splits(int64_t n, int m1, int m2) {
-    const int64_t tiles = (int64_t)((m1 + 63) / 64) * ((m2 + 63) / 64);
-    const int64_t want = (4096 + tiles - 1) / tiles;
-    return static_cast<int>(std::min<int64_t>(std::min<int64_t>(want, 1024), std::max<int64_t>(1, n / 256)));
-}
-
 struct SolveLayout {
     size_t x, q, u, w, z64, t64, b64;
     size_t S, V, G, T, wv, d, theta, rr, phase, order;
-    size_t eta, nu, fwork, gpart, rpart, jwork;
+    size_t eta, nu, fwork, gpart, rpart, jwork, tree;
     size_t fwork_bytes, gpart_bytes, rpart_bytes, jwork_bytes, total;
     int rgrid;
 };
@@ -98,6 +89,9 @@ int solve_layout(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     L->gpart = take(L->gpart_bytes);
     L->rpart = take(L->rpart_bytes);
     L->jwork = take(L->jwork_bytes);
+    // TSQR: the panel and its projection use the FP64 blocks of the Rayleigh-Ritz step
+    // (n x n_b each, free during the orthogonalisation); the reduction tree needs its own
+    L->tree = take(p->orth == CHEBFD_ORTH_TSQR ? tsqr_tree_bytes(H->n, tsqr_panel_width(p->n_b)) : 0);
     L->total = at;
     return CHEBFD_OK;
 }
@@ -119,6 +113,7 @@ int check_params(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     CHEBFD_REQUIRE(std::isfinite(p->lam_L) && std::isfinite(p->lam_R) && p->lam_L < p->lam_R,
                    "search interval invalid");
     CHEBFD_REQUIRE(p->tol > 0.0, "tol must be positive");
+    CHEBFD_REQUIRE(p->orth == CHEBFD_ORTH_SVQB || p->orth == CHEBFD_ORTH_TSQR, "orth = %d invalid", p->orth);
     return CHEBFD_OK;
 }
 
@@ -176,6 +171,47 @@ int chebfd_update(int64_t n, int32_t n_b, int32_t m1, int32_t m2, int32_t prec_a
                    "A and Z overlap");
     return launch_update(d_a, prec_a, n_b, d_m, ldm, d_z, prec_z, n_b, n, m1, m2,
                          static_cast<hipStream_t>(stream));
+}
+
+int chebfd_tsqr_query(int64_t n, int32_t m, int32_t n_b, size_t *work_bytes) {
+    clear_error();
+    CHEBFD_REQUIRE(work_bytes, "NULL argument");
+    CHEBFD_REQUIRE(n >= 1 && m >= 1 && m <= n && m <= 4096, "TSQR sizes n = %lld, m = %d invalid",
+                   (long long)n, m);
+    CHEBFD_REQUIRE(n_b >= 1 && n_b <= 128 && (n_b & (n_b - 1)) == 0, "n_b = %d invalid", n_b);
+    const size_t pw = tsqr_panel_width(n_b);
+    *work_bytes = 2 * al((size_t)n * pw * 16) + al(tsqr_tree_bytes(n, (int)pw)) + 2 * al((size_t)m * pw * 16) +
+                  al(tsqr_gpart_bytes(n, m, n_b));
+    return CHEBFD_OK;
+}
+
+int chebfd_tsqr(int64_t n, int32_t m, int32_t n_b, int32_t prec, const void *d_y, void *d_q, double *d_r,
+                int32_t ld_r, void *d_work, size_t work_bytes, void *stream) {
+    size_t need;
+    int rc = chebfd_tsqr_query(n, m, n_b, &need);
+    if (rc) return rc;
+    CHEBFD_REQUIRE(prec == CHEBFD_PREC_FP64 || prec == CHEBFD_PREC_MIXED, "prec invalid");
+    CHEBFD_REQUIRE(d_y && d_q && d_r && d_work, "NULL buffer");
+    CHEBFD_REQUIRE(ld_r >= m, "ld_r = %d < m = %d", ld_r, m);
+    const size_t es = vec_elem_bytes(prec);
+    CHEBFD_REQUIRE(aligned(d_y, es) && aligned(d_q, es) && aligned(d_r, 16) && aligned(d_work, 256),
+                   "misaligned buffer");
+    const size_t vbytes = es * (size_t)n * ((m + n_b - 1) / n_b * n_b);
+    CHEBFD_REQUIRE(!overlap(d_y, vbytes, d_q, vbytes), "Y and Q overlap");
+    if (work_bytes < need) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "TSQR workspace %zu < %zu", work_bytes, need);
+    const size_t pw = tsqr_panel_width(n_b);
+    char *base = static_cast<char *>(d_work);
+    size_t at = 0;
+    auto take = [&](size_t bytes) { double *h = reinterpret_cast<double *>(base + at); at += al(bytes); return h; };
+    TsqrWork w;
+    w.T = take((size_t)n * pw * 16);
+    w.U = take((size_t)n * pw * 16);
+    w.tree = take(tsqr_tree_bytes(n, (int)pw));
+    w.C1 = take((size_t)m * pw * 16);
+    w.C2 = take((size_t)m * pw * 16);
+    w.ldc = m;
+    w.gpart = take(tsqr_gpart_bytes(n, m, n_b));
+    return tsqr_blocked(n, m, n_b, prec, d_y, prec, d_q, d_r, ld_r, w, static_cast<hipStream_t>(stream));
 }
 
 int chebfd_heev_query(int32_t m, size_t *work_bytes) {
@@ -305,6 +341,41 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
         return CHEBFD_OK;
     };
 
+    // TSQR of the stage's basis X (all ns columns) into Q; columns whose part
+    // outside the span of the earlier ones is at the resolved level
+    // (|R_kk|^2 <= tau ||y_k||^2) are dropped and the kept ones factorised again.
+    // On return X holds the k kept orthonormal directions (the buffers swap).
+    std::vector<double> hinfo(2 * (size_t)ns), hsel;
+    auto orth_tsqr = [&](Stage &g, int *k) -> int {
+        int r;
+        const TsqrWork w{DD(L.b64), DD(L.t64), DD(L.tree), DD(L.V), DD(L.G), ns, DD(L.gpart)};
+        if ((r = tsqr_blocked(n, g.ns, g.nb, g.prec, g.X, g.prec, g.Q, DD(L.S), ns, w, s))) return r;
+        if ((r = launch_tsqr_colinfo(g.ns, DD(L.S), ns, DD(L.T), s))) return r;
+        CHEBFD_HIP(hipMemcpyAsync(hinfo.data(), DD(L.T), sizeof(double) * 2 * g.ns, hipMemcpyDeviceToHost, s));
+        CHEBFD_HIP(hipStreamSynchronize(s));
+        const double tau = tau_for(g.prec);
+        std::vector<int> keep;
+        for (int c = 0; c < g.ns; ++c) {
+            if (!std::isfinite(hinfo[2 * c]) || !std::isfinite(hinfo[2 * c + 1]))
+                CHEBFD_FAIL(CHEBFD_ENUMERIC, "TSQR: non-finite R");
+            if (hinfo[2 * c] > tau * hinfo[2 * c + 1]) keep.push_back(c);
+        }
+        const int kk = static_cast<int>(keep.size());
+        if (kk == 0) CHEBFD_FAIL(CHEBFD_ENUMERIC, "TSQR: no independent column");
+        if (kk < g.ns) {
+            // Y's kept columns into Q (a selection matrix through the update), then TSQR back into X
+            hsel.assign((size_t)2 * ns * kk, 0.0);
+            for (int c = 0; c < kk; ++c) hsel[2 * ((size_t)c * ns + keep[c])] = 1.0;
+            CHEBFD_HIP(hipMemcpyAsync(DD(L.T), hsel.data(), sizeof(double) * hsel.size(), hipMemcpyHostToDevice, s));
+            if ((r = launch_update(g.X, g.prec, g.nb, DD(L.T), ns, g.Q, g.prec, g.nb, n, g.ns, kk, s))) return r;
+            if ((r = tsqr_blocked(n, kk, g.nb, g.prec, g.Q, g.prec, g.X, DD(L.S), ns, w, s))) return r;
+        } else {
+            std::swap(g.X, g.Q);
+        }
+        *k = kk;
+        return CHEBFD_OK;
+    };
+
     // Iterations of one stage until its convergence rule holds or max_iter is
     // reached.  prev: in-window converged count the first test compares with.
     // On return the stage's X holds the last kept basis, S its Ritz vectors
@@ -347,11 +418,15 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
                 count_est = acc / ns;   // n * sum g c mu~ with mu~ = mu / (n R)
             }
 
-            // --- SVQB twice ---
+            // --- orthogonalisation: SVQB twice, or TSQR ---
             CHEBFD_HIP(hipEventRecord(ev[1].e[0], s));
-            int k1 = 0;
-            if ((r = svqb(g, g.X, g.ns, g.Q, &k1))) return r;
-            if ((r = svqb(g, g.Q, k1, g.X, &k2))) return r;
+            if (p->orth == CHEBFD_ORTH_TSQR) {
+                if ((r = orth_tsqr(g, &k2))) return r;
+            } else {
+                int k1 = 0;
+                if ((r = svqb(g, g.X, g.ns, g.Q, &k1))) return r;
+                if ((r = svqb(g, g.Q, k1, g.X, &k2))) return r;
+            }
             CHEBFD_HIP(hipEventRecord(ev[1].e[1], s));
 
             // --- Rayleigh-Ritz on the k2 kept directions (FP64 products) ---
