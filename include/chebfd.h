@@ -391,6 +391,8 @@ int chebfd_heev(int32_t m, double *d_a, int32_t lda, double *d_v, int32_t ldv, d
  * then the other Ritz values (ascending); d_Z (n x n_s c128 column-major, may be
  * NULL): the Ritz vectors in the same order, each scaled so that its largest
  * entry is real positive; columns beyond the kept directions are zero.
+ * With CHEBFD_VERBOSE=1 in the environment one progress line per iteration
+ * goes to stderr.
  */
 #define CHEBFD_ORTH_SVQB 0
 #define CHEBFD_ORTH_TSQR 1

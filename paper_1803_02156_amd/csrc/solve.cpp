@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -264,6 +266,9 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     if (work_bytes < L.total) CHEBFD_FAIL(CHEBFD_EWORKSPACE, "solve workspace %zu < %zu", work_bytes, L.total);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // CHEBFD_VERBOSE=1 in the environment: one progress line per iteration on stderr
+    const char *venv = std::getenv("CHEBFD_VERBOSE");
+    const bool verbose = venv && venv[0] == '1';
     char *base = static_cast<char *>(d_work);
     auto D = [&](size_t off) { return static_cast<void *>(base + off); };
     auto DD = [&](size_t off) { return reinterpret_cast<double *>(base + off); };
@@ -507,6 +512,11 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
             // the in-interval pairs whose residual already places them in the interval
             if (stage1 && it >= 2 && settled > 0.75 * g.ns) return CHEBFD_SUBSPACE_SMALL;
             const bool unres_settled = !(unres_min < INFINITY) || unres_min > 0.5 * prev_unres;
+            if (verbose)
+                std::fprintf(stderr,
+                             "chebfd_solve: %s iteration %d: %d kept, %d in the interval, %d converged, "
+                             "smallest unresolved residual %.3g; filter %.3f s, orthogonalisation %.3f s\n",
+                             stage1 ? "stage 1" : "stage 2", it, k2, inwin, conv, unres_min, t_phase[0], t_phase[1]);
             if (conv == prev && unres_settled) return CHEBFD_OK;
             // stage 1 of a mixed run also ends when the residuals stop falling (storage floor)
             if (stage1 && g.prec != CHEBFD_PREC_FP64 && inwin > 0 && inwin == prev_inwin && conv == prev &&
