@@ -173,7 +173,9 @@ int chebfd_random_phase(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t 
  * (with <a, b> = sum_i conj(a_i) b_i, FP64 accumulation, deterministic
  * summation order); row 0 is not written.  May be NULL together (moments not
  * needed is not faster: they are computed in the same pass).
- * d_work: chebfd_filter_query bytes.  n_b in {1,2,4,8,16,32,64,128},
+ * d_work: chebfd_filter_query bytes (the partial sums of the dot products and
+ * one progress word per workgroup of the window kernel, tagged per launch, so
+ * nothing has to start at zero).  n_b in {1,2,4,8,16,32,64,128},
  * n_s % n_b == 0, n_p >= 0, gamma[n_p + 1] on the host.
  * Buffers must be 256-byte aligned and must not overlap.
  */
@@ -185,9 +187,11 @@ int chebfd_filter_query(const chebfd_matrix *H, int32_t n_b, size_t *work_bytes)
  * what they stage in LDS):
  *   CHEBFD_KERNEL_WINDOW   one workgroup per CU sweeps a contiguous row range and
  *                          gathers U from a window of U rows staged in LDS (FP64
- *                          n_b = 32 and c64 n_b = 64; C = 32; rows of at most 13
- *                          entries; window_local[] >= 700 for the tile height:
- *                          32 rows for both)
+ *                          n_b = 32, c64 n_b = 64, and c64 n_b = 32 on large
+ *                          matrices; C = 32; rows of at most 13 entries;
+ *                          window_local[] >= 700 for the tile height); the
+ *                          ranges of one XCD are held within a few tiles of
+ *                          each other through progress words in the workspace
  *   CHEBFD_KERNEL_LDS      the tile's matrix slots staged in LDS, U gathered from
  *                          memory (rows of up to 16 entries, C <= 32)
  *   CHEBFD_KERNEL_ROW      one row per wavefront group (n_b >= 32, wider rows)
@@ -226,7 +230,8 @@ int chebfd_filter_unfused(const chebfd_matrix *H, double alpha, double beta, con
  * chebfd_filter without a workspace argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation): the partial dot-product sums that the step kernels
- * hand from one launch to the next live in a static device array of 4 MiB
+ * hand from one launch to the next, and the window kernel's progress words,
+ * live in a static device array of 4 MiB
  * (one copy per device, held until the process ends).  Every call on a device
  * shares that device's array: calls that overlap on one device (on different
  * streams, or from several threads) race; calls in sequence on a stream are

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -182,6 +183,16 @@ static MatrixLayout matrix_layout(const SellPlan &p, int prec, int C) {
 }  // namespace chebfd
 
 using namespace chebfd;
+
+namespace chebfd {
+int32_t next_step_epoch() {
+    static std::atomic<uint32_t> counter{0};
+    for (;;) {
+        const uint32_t v = (counter.fetch_add(1, std::memory_order_relaxed) + 1) & 0x7fffffffu;
+        if (v != 0) return static_cast<int32_t>(v);
+    }
+}
+}  // namespace chebfd
 
 extern "C" {
 
@@ -455,9 +466,14 @@ int chebfd_random_phase(const chebfd_matrix *H, int32_t m, int32_t n_b, int32_t 
                                static_cast<hipStream_t>(stream));
 }
 
-// workspace of the filter: two partial buffers [3*n_b][G] (double buffered)
+// workspace of the filter: two partial buffers [3*n_b][G] (double buffered),
+// then one progress word per workgroup (the window kernel's lead control)
+static size_t filter_part_bytes(int nb, int G) { return round_up(sizeof(double) * 3 * nb * (size_t)G, 256); }
 static size_t filter_work_bytes(int nb, int G) {
-    return 2 * round_up(sizeof(double) * 3 * nb * (size_t)G, 256);
+    return 2 * filter_part_bytes(nb, G) + round_up(sizeof(int64_t) * (size_t)G, 256);
+}
+static int64_t *filter_prog(void *d_work, int nb, int G) {
+    return reinterpret_cast<int64_t *>(static_cast<char *>(d_work) + 2 * filter_part_bytes(nb, G));
 }
 
 // Launch geometry of the step kernels.  The window kernel (U staged in LDS)
@@ -730,7 +746,9 @@ static int filter_run(const chebfd_matrix *H, double alpha, double beta, const d
     const size_t blk = vec_elem_bytes(prec) * (size_t)H->n * n_b;
     double *part[2];
     part[0] = static_cast<double *>(d_work);
-    part[1] = reinterpret_cast<double *>(static_cast<char *>(d_work) + need / 2);
+    part[1] = reinterpret_cast<double *>(static_cast<char *>(d_work) + filter_part_bytes(n_b, G));
+    int64_t *prog = filter_prog(d_work, n_b, G);
+    (void)need;
     const int nblocks = n_s / n_b;
     const int64_t count = H->n * (int64_t)n_b;
 
@@ -744,6 +762,8 @@ static int filter_run(const chebfd_matrix *H, double alpha, double beta, const d
         a.red_eta = pend_eta;
         a.red_nu = pend_nu;
         a.G_prev = G;
+        a.prog = prog;
+        a.epoch = next_step_epoch();
         pend_part = part[flip];
         if (d_eta) {
             pend_eta = d_eta + 2 * ((int64_t)p * n_s + (int64_t)b * n_b);
@@ -930,6 +950,8 @@ int chebfd_op(const chebfd_matrix *H, double alpha, double beta, double gamma, i
     a.Y = d_y;
     a.g2 = gamma;
     a.part_out = static_cast<double *>(d_work);
+    a.prog = filter_prog(d_work, n_b, G);
+    a.epoch = next_step_epoch();
     return launch_any(H, prec, n_b, kModeStep, a, geo, static_cast<hipStream_t>(stream));
 }
 

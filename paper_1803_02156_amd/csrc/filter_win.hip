@@ -23,6 +23,7 @@
 // [CPL (t % LPR), CPL (t % LPR) + CPL) of row t / LPR of the tile.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <type_traits>
 
@@ -38,6 +39,13 @@ using namespace step_io;
 constexpr int kWinThreads = 1024;
 constexpr int kXcdCount = 8;
 constexpr int kWinLdsLimit = 160 * 1024;
+// Lead control (see the kernel): every kWinCheckEvery tiles the first wave of a
+// workgroup publishes its progress and reads that of the other workgroups of its
+// XCD; more than kWinMaxLead tiles ahead of the slowest, it waits for it,
+// polling at most kWinMaxPolls times.
+constexpr int kWinCheckEvery = 32;
+constexpr int kWinMaxLead = 4;
+constexpr int kWinMaxPolls = 200;
 
 template <typename T, int NB>
 struct WinShape {
@@ -372,10 +380,46 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
         __syncthreads();
         buf ^= 1;
     };
+    // Lead control between the sweep ranges of one XCD.  The row order deals
+    // neighbouring pencils of the lattice to the ranges of one XCD at equal
+    // offsets, so the gathers that leave the window read rows that another
+    // range has just loaded into the shared L2 -- as long as the ranges advance
+    // together; left alone they drift apart by far more than the few tiles the
+    // L2 holds.  Every kWinCheckEvery tiles the first wave publishes
+    // (launch tag, tiles done) in prog[x per + k] (workgroup w = x + 8 k on XCD
+    // x) and, while the workgroup is more than kWinMaxLead tiles ahead of the
+    // slowest range of its XCD that has started this launch, polls again (a
+    // bounded wait: it only costs time).  Only the first wave touches the
+    // counters (a wave-uniform branch); the others wait at the tile's barrier.
+    const int per = G / kXcdCount;
+    const bool lead = a.prog != nullptr && G % kXcdCount == 0 && per <= 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int64_t *const my_prog = lead ? a.prog + (w % kXcdCount) * per + w / kXcdCount : nullptr;
+    const int64_t *const xcd_prog = lead ? a.prog + (w % kXcdCount) * per : nullptr;
+    const int64_t tag = static_cast<int64_t>(a.epoch) << 32;
+    auto check = [&](int done) {
+        __hip_atomic_store(my_prog, tag | static_cast<uint32_t>(done), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int k = (tid & 63) % per;
+        for (int poll = 0; poll < kWinMaxPolls; ++poll) {
+            const int64_t v = __hip_atomic_load(xcd_prog + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // a range that has not started this launch (older tag) holds no one back
+            int d = static_cast<int32_t>(v >> 32) == a.epoch ? static_cast<int>(v & 0xffffffff) : INT_MAX;
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) d = min(d, __shfl_xor(d, m));
+            if (done - d <= kWinMaxLead) break;
+            __builtin_amdgcn_s_sleep(16);
+        }
+    };
+
     // full tiles, then the ragged last tile of the matrix (if it is in this range)
     const int te_full = te < n32 / TR ? te : (n32 / TR > tb ? n32 / TR : tb);
-    for (int tile = tb; tile < te_full; ++tile) tile_body(tile, std::true_type{});
+    for (int tile = tb; tile < te_full; ++tile) {
+        if (lead && wave == 0 && (tile - tb) % kWinCheckEvery == 0) check(tile - tb);
+        tile_body(tile, std::true_type{});
+    }
     for (int tile = te_full; tile < te; ++tile) tile_body(tile, std::false_type{});
+    if (lead && wave == 0)
+        __hip_atomic_store(my_prog, tag | static_cast<uint32_t>(te - tb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     if constexpr (!mode_dots(MODE)) return;
     // workgroup reduction over the TR lanes of each column, fixed order;

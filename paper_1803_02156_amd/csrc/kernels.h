@@ -43,7 +43,11 @@ struct StepArgs {
     double *red_nu;             // destination of the reduced nu [NB]
     int32_t G_prev;
     int32_t uniform_width;      // every chunk has this many slots per row (0: read chunk_width)
+    int64_t *prog;              // [G] progress words of the window kernel's lead control, or null
+    int32_t epoch;              // this launch's tag in prog (nonzero, distinct from recent launches)
 };
+// A fresh launch tag for StepArgs::epoch (host, thread-safe).
+int32_t next_step_epoch();
 
 int launch_step(int prec, int nb, int mode, const StepArgs &a, int G, hipStream_t s);
 
