@@ -423,24 +423,27 @@ def main():
                    "fused_speedup": round(u_step / step_ms, 3)}
         log(f"unfused filter: {u_step:.2f} ms per step (fused {step_ms:.2f} ms: x{u_step / step_ms:.2f})")
 
-    # attainable HBM bandwidth (the STREAM analogue of Table 2) over 2 x 4 GiB: the plain
-    # copy, the non-temporal copy (four 16-byte elements per thread) and a read-only pass
+    # attainable HBM bandwidth (the STREAM analogue of Table 2) over arrays of 4 GiB: the
+    # plain copy, the non-temporal copy (four 16-byte elements per thread), a read-only
+    # pass and the triad a = b + s c (two reads per write, about the step's own mix)
     cnt = 1 << 29
     pa = torch.empty(cnt, dtype=torch.float64, device="cuda")
     pb = torch.ones(cnt, dtype=torch.float64, device="cuda")
+    pc = torch.ones(cnt, dtype=torch.float64, device="cuda")
     probes = {}
-    for kind, name, nbytes in ((0, "copy", 16 * cnt), (2, "copy_nt", 16 * cnt), (3, "read", 8 * cnt)):
-        P.chebfd_probe_stream(kind, pa, pb)
+    for kind, name, nbytes in ((0, "copy", 16 * cnt), (2, "copy_nt", 16 * cnt), (3, "read", 8 * cnt),
+                               (1, "triad", 24 * cnt)):
+        P.chebfd_probe_stream(kind, pa, pb, pc)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(bf.stream)
         for _ in range(10):
-            P.chebfd_probe_stream(kind, pa, pb)
+            P.chebfd_probe_stream(kind, pa, pb, pc)
         e1.record(bf.stream)
         torch.cuda.synchronize()
         probes[name] = round(10 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
     copy_gbs = max(probes["copy"], probes["copy_nt"])
     log(f"probes: {probes}")
-    del pa, pb
+    del pa, pb, pc
     del bf, M
     torch.cuda.empty_cache()
 
