@@ -431,13 +431,13 @@ def main():
     pb = torch.ones(cnt, dtype=torch.float64, device="cuda")
     pc = torch.ones(cnt, dtype=torch.float64, device="cuda")
     probes = {}
-    for kind, name, nbytes in ((0, "copy", 16 * cnt), (2, "copy_nt", 16 * cnt), (3, "read", 8 * cnt),
-                               (1, "triad", 24 * cnt)):
-        P.chebfd_probe_stream(kind, pa, pb, pc)
+    for pkind, name, nbytes in ((0, "copy", 16 * cnt), (2, "copy_nt", 16 * cnt), (3, "read", 8 * cnt),
+                                (1, "triad", 24 * cnt)):
+        P.chebfd_probe_stream(pkind, pa, pb, pc)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(bf.stream)
         for _ in range(10):
-            P.chebfd_probe_stream(kind, pa, pb, pc)
+            P.chebfd_probe_stream(pkind, pa, pb, pc)
         e1.record(bf.stream)
         torch.cuda.synchronize()
         probes[name] = round(10 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
