@@ -49,8 +49,10 @@ __device__ inline void store_c(void *base, int prec, int64_t idx, double2 v) {
     }
 }
 
+// nb is a power of two (the launchers check): shifts instead of an integer division
 __device__ inline int64_t blocked_index(int64_t n, int nb, int64_t i, int c) {
-    return ((int64_t)(c / nb) * n + i) * nb + (c % nb);
+    const int lg = __ffs(nb) - 1;
+    return ((int64_t)(c >> lg) * n + i) * nb + (c & (nb - 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -671,8 +673,11 @@ __global__ __launch_bounds__(kT) void scale_columns_kernel(void *Z, int prec, in
 
 }  // namespace
 
+static bool pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
+
 int launch_gram(const void *A, int prec_a, int nb_a, const void *B, int prec_b, int nb_b, int64_t n,
                 int m1, int m2, double *part, int nsplit, double *S, int ld, hipStream_t s) {
+    if (!pow2(nb_a) || !pow2(nb_b)) CHEBFD_FAIL(CHEBFD_EINVAL, "block widths %d, %d must be powers of two", nb_a, nb_b);
     const int ta = (m1 + kGT - 1) / kGT, tb = (m2 + kGT - 1) / kGT;
     // A^H A: Hermitian, only the tiles on and above the diagonal
     const int herm = (A == B && prec_a == prec_b && nb_a == nb_b && m1 == m2) ? 1 : 0;
@@ -697,6 +702,7 @@ size_t gram_part_bytes(int m1, int m2, int nsplit) {
 
 int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm, void *Z, int prec_z,
                   int nb_z, int64_t n, int m1, int m2, hipStream_t s) {
+    if (!pow2(nb_a) || !pow2(nb_z)) CHEBFD_FAIL(CHEBFD_EINVAL, "block widths %d, %d must be powers of two", nb_a, nb_z);
     const dim3 grid(static_cast<unsigned>((n + kGT - 1) / kGT), (m2 + kGT - 1) / kGT);
     hipLaunchKernelGGL(update_kernel, grid, dim3(kT), 0, s, A, prec_a, nb_a, M, ldm, Z, prec_z, nb_z,
                        n, m1, m2);
@@ -821,6 +827,7 @@ int launch_convert(const void *src, int prec_src, void *dst, int prec_dst, int64
 int launch_random_phase(void *X, int prec, int64_t n, int nb, int c_begin, int c_end, uint64_t seed,
                         uint64_t col0, const int32_t *perm, hipStream_t s) {
     if (c_end <= c_begin) return CHEBFD_OK;
+    if (!pow2(nb)) CHEBFD_FAIL(CHEBFD_EINVAL, "block width %d must be a power of two", nb);
     hipLaunchKernelGGL(random_phase_kernel, dim3(grid_cap(n * (c_end - c_begin), 65536)), dim3(kT), 0, s,
                        X, prec, n, nb, c_begin, c_end, seed, col0, perm);
     CHEBFD_HIP(hipGetLastError());
@@ -828,6 +835,7 @@ int launch_random_phase(void *X, int prec, int64_t n, int nb, int c_begin, int c
 }
 
 int launch_fix_phases(void *Z, int prec, int64_t n, int nb, int m, double *phase, hipStream_t s) {
+    if (!pow2(nb)) CHEBFD_FAIL(CHEBFD_EINVAL, "block width %d must be a power of two", nb);
     hipLaunchKernelGGL(phase_argmax_kernel, dim3(m < 1024 ? m : 1024), dim3(kT), 0, s, Z, prec, n, nb, m,
                        phase);
     CHEBFD_HIP(hipGetLastError());
