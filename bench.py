@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--solve-count", type=float, default=100.0,
                     help="eigenvalue count the symmetric search interval is sized for")
     ap.add_argument("--solve-n_b", type=int, default=32)
+    ap.add_argument("--solve-runs", type=str, default="fp64_heuristic,mixed_heuristic,mixed_learned,mixed_heuristic_tsqr",
+                    help="comma-separated subset of the time-to-converged runs")
+    ap.add_argument("--solve-n_s", type=int, default=0,
+                    help="subspace size of every time-to-converged run (0: from the heuristic / the network)")
     ap.add_argument("--beyond-hbm-lattice", type=str, default="128x128x64",
                     help="lattice of the host-resident search-space leg ('' skips it)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
@@ -181,7 +185,8 @@ def interval_for_count(P, M, target, seed=7, n_steps=1024, R=16):
     return 0.5 * (a + b), count(0.5 * (a + b))
 
 
-def time_to_converged(P, lattice, W, n_b, target):
+def time_to_converged(P, lattice, W, n_b, target, n_s_fixed=0,
+                      which=("fp64_heuristic", "mixed_heuristic", "mixed_learned", "mixed_heuristic_tsqr")):
     """Full ChebFD runs (filter, SVQB, Rayleigh-Ritz, residuals, restarts) on one
     matrix and interval: FP64 and mixed precision with the heuristic's (n_p, n_s)
     (the fallback rule), mixed precision with the learned (n_p, n_s), and mixed
@@ -201,6 +206,8 @@ def time_to_converged(P, lattice, W, n_b, target):
     f, cnt_f, _, _ = P.chebfd_features(M64, -delta, delta, 7)
     hp, hs = PR.choose(None, f, cnt_f, pred["kappa"])
     lp, ls = PR.choose(pred, f, cnt_f, pred["kappa"])
+    if n_s_fixed > 0:
+        hs = ls = n_s_fixed
     out = {"workload": f"Topi-{Nx}-{Ny}-{Nz} (n={M64.n}, W={W}), interval [-{delta:.6g}, {delta:.6g}] "
                        f"(KPM count estimate {cnt:.1f}, 2048 moments), n_b={n_b}, max 12 iterations",
            "interval": [-delta, delta], "count_est_kpm": cnt, "count_est_features": cnt_f,
@@ -209,6 +216,8 @@ def time_to_converged(P, lattice, W, n_b, target):
     for name, M, n_p, n_s, orth in (("fp64_heuristic", M64, hp, hs, "svqb"), ("mixed_heuristic", M32, hp, hs, "svqb"),
                                     ("mixed_learned", M32, lp, ls, "svqb"),
                                     ("mixed_heuristic_tsqr", M32, hp, hs, "tsqr")):
+        if name not in which:
+            continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = P.chebfd_solve(M, M64, -delta, delta, n_s, n_p, n_b, seed=43, max_iter=12, want_vectors=False,
@@ -227,8 +236,10 @@ def time_to_converged(P, lattice, W, n_b, target):
         }
         log(f"solve {name} (n_p {n_p}, n_s {n_s}): {dt:.2f} s, status {r.status}, {st.iterations} iterations, "
             f"{nf} pairs")
-    ref = runs["fp64_heuristic"]
+    ref = runs.get("fp64_heuristic")
     for name in ("mixed_heuristic", "mixed_learned", "mixed_heuristic_tsqr"):
+        if name not in runs or ref is None:
+            continue
         r = runs[name]
         o = out[name]
         o["all_pairs_of_fp64_run"] = bool(r.status == 0 and ref.status == 0 and r.n_found >= ref.n_found > 0)
@@ -514,7 +525,8 @@ def main():
 
     solve = None
     if args.solve_lattice:
-        solve, H_small = time_to_converged(P, args.solve_lattice, args.solve_W, args.solve_n_b, args.solve_count)
+        solve, H_small = time_to_converged(P, args.solve_lattice, args.solve_W, args.solve_n_b, args.solve_count,
+                                           args.solve_n_s, tuple(args.solve_runs.split(",")))
         torch.cuda.empty_cache()
 
     hostres = None
