@@ -240,24 +240,36 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int nb_a, con
 #pragma unroll
             for (int q = 0; q < 2; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = 0; k0 < m1; k0 += kGK) {
-        for (int t = threadIdx.x; t < kGT * kGK; t += kT) {
+    // stages of kGK columns of A (64 rows) and kGK rows of M (64 columns): the next
+    // stage's global loads are issued before the current stage's products
+    constexpr int kPer = kGT * kGK / kT;   // elements per thread and operand
+    RA pa[kPer];
+    double2 pm[kPer];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int t = threadIdx.x + q * kT;
             const int rr = t / kGK, kk = t % kGK;
             const int64_t i = i0 + rr;
-            double2 v = {0.0, 0.0};
-            if (i < n && k0 + kk < m1) {
-                const RA r = static_cast<const RA *>(A)[blocked_index(n, nb_a, i, k0 + kk)];
-                v = double2{(double)r.x, (double)r.y};
-            }
-            sa[rr][kk] = v;
+            RA va{};
+            if (i < n && k0 + kk < m1) va = static_cast<const RA *>(A)[blocked_index(n, nb_a, i, k0 + kk)];
+            pa[q] = va;
+            const int km = t / kGT, cc = t % kGT;
+            double2 vm{0.0, 0.0};
+            if (k0 + km < m1 && c0 + cc < m2) vm = Mc[(int64_t)(c0 + cc) * ldm + k0 + km];
+            pm[q] = vm;
         }
-        for (int t = threadIdx.x; t < kGK * kGT; t += kT) {
-            const int kk = t / kGT, cc = t % kGT;
-            double2 v = {0.0, 0.0};
-            if (k0 + kk < m1 && c0 + cc < m2) v = Mc[(int64_t)(c0 + cc) * ldm + k0 + kk];
-            sm[kk][cc] = v;
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < m1; k0 += kGK) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int t = threadIdx.x + q * kT;
+            sa[t / kGK][t % kGK] = double2{(double)pa[q].x, (double)pa[q].y};
+            sm[t / kGT][t % kGT] = pm[q];
         }
         __syncthreads();
+        if (k0 + kGK < m1) fetch(k0 + kGK);
 #pragma unroll
         for (int kb = 0; kb < kGK; kb += 4) {
             const int kk = kb + lane / 16;
