@@ -345,12 +345,13 @@ std::vector<int64_t> tree_rows(int64_t n, int pw) {
     return r;
 }
 
+// the LDS size above the default is a per-device attribute of the kernel: set
+// it on every use (the current device may change between calls)
 template <int PW>
 bool set_apply_attr() {
-    static const bool ok = hipFuncSetAttribute(reinterpret_cast<const void *>(tsqr_apply_kernel<PW>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               static_cast<int>(apply_lds_bytes(PW))) == hipSuccess;
-    return ok;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(tsqr_apply_kernel<PW>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(apply_lds_bytes(PW))) == hipSuccess;
 }
 
 // QR of one panel: src (rows n, cols <= PW, element (i, c) at src[i ld + c])
