@@ -86,65 +86,76 @@ __device__ inline void gram_tile(int t, int tiles_a, bool herm, int *ta, int *tb
 // a branch and kept the prefetch registers FP64 wide (two waves per SIMD
 // instead of three; 287 -> 162 ms for a 33.5 M x 256 c64 product).  Stages stay
 // in registers in the storage type until they go to LDS as FP64.
-template <typename TA, typename TB>
+template <typename TA, typename TB, int BW>
 __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int nb_a, const void *B, int nb_b, int64_t n,
                                                    int m1, int m2, int tiles_a, int herm, int64_t rows_per_split,
                                                    double *part) {
+    // output tile 64 (columns of A) x BW (columns of B); BW = 32 for products of at
+    // most 32 columns of B (Rayleigh-Ritz and TSQR panels), so no wave multiplies zeros
     constexpr int KG = kGK;
+    constexpr int NY = BW / 32;                // 16-column MFMA tiles per wave
     using RA = typename std::conditional<std::is_same<TA, double>::value, double2, float2>::type;
     using RB = typename std::conditional<std::is_same<TB, double>::value, double2, float2>::type;
     __shared__ double2 sa[KG][kGT];
-    __shared__ double2 sb[KG][kGT];
+    __shared__ double2 sb[KG][BW];
     const int tile = blockIdx.x;
     const int split = blockIdx.y;
     int ta, tb;
     gram_tile(tile, tiles_a, herm != 0, &ta, &tb);
-    const int a0 = ta * kGT, b0 = tb * kGT;
+    const int a0 = ta * kGT, b0 = tb * BW;
     const int64_t r0 = (int64_t)split * rows_per_split;
     const int64_t r1 = r0 + rows_per_split < n ? r0 + rows_per_split : n;
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int wa = (wv & 1) * 32, wb = (wv >> 1) * 32;  // wave's 32 x 32 sub-tile
+    const int wa = (wv & 1) * 32, wb = (wv >> 1) * (BW / 2);  // wave's 32 x BW/2 sub-tile
 
     // two accumulators per 16 x 16 tile: real and imaginary part of the sum
-    d4v acc[2][2][2];
+    d4v acc[2][NY][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < NY; ++y)
 #pragma unroll
             for (int q = 0; q < 2; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
 
-    // Stages of KG rows x 64 columns of A and of B (zero outside the matrices):
-    // the next stage's global loads are issued before the current stage's
-    // products, so their latency hides behind the matrix-core work.
-    constexpr int kPer = KG * kGT / kT;   // elements per thread and matrix
-    RA ra[kPer];
-    RB rb2[kPer];
+    // Stages of KG rows x 64 columns of A and KG rows x BW columns of B (zero
+    // outside the matrices): the next stage's global loads are issued before the
+    // current stage's products, so their latency hides behind the matrix-core work.
+    constexpr int kPerA = KG * kGT / kT, kPerB = KG * BW / kT;   // elements per thread
+    RA ra[kPerA];
+    RB rb2[kPerB];
     auto fetch = [&](int64_t rbase) {
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < kPerA; ++q) {
             const int t = threadIdx.x + q * kT;
             const int rr = t / kGT, cc = t % kGT;
             const int64_t i = rbase + rr;
             RA va{};
-            RB vb{};
-            if (i < r1) {
-                if (a0 + cc < m1) va = static_cast<const RA *>(A)[blocked_index(n, nb_a, i, a0 + cc)];
-                if (b0 + cc < m2) vb = static_cast<const RB *>(B)[blocked_index(n, nb_b, i, b0 + cc)];
-            }
+            if (i < r1 && a0 + cc < m1) va = static_cast<const RA *>(A)[blocked_index(n, nb_a, i, a0 + cc)];
             ra[q] = va;
+        }
+#pragma unroll
+        for (int q = 0; q < kPerB; ++q) {
+            const int t = threadIdx.x + q * kT;
+            const int rr = t / BW, cc = t % BW;
+            const int64_t i = rbase + rr;
+            RB vb{};
+            if (i < r1 && b0 + cc < m2) vb = static_cast<const RB *>(B)[blocked_index(n, nb_b, i, b0 + cc)];
             rb2[q] = vb;
         }
     };
     if (r0 < r1) fetch(r0);
     for (int64_t rb = r0; rb < r1; rb += KG) {
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < kPerA; ++q) {
             const int t = threadIdx.x + q * kT;
             sa[t / kGT][t % kGT] = double2{(double)ra[q].x, (double)ra[q].y};
-            sb[t / kGT][t % kGT] = double2{(double)rb2[q].x, (double)rb2[q].y};
+        }
+#pragma unroll
+        for (int q = 0; q < kPerB; ++q) {
+            const int t = threadIdx.x + q * kT;
+            sb[t / BW][t % BW] = double2{(double)rb2[q].x, (double)rb2[q].y};
         }
         __syncthreads();
         if (rb + KG < r1) fetch(rb + KG);
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int nb_a, const
             for (int x = 0; x < 2; ++x) {
                 const double2 av = sa[kk][wa + 16 * x + lane % 16];
 #pragma unroll
-                for (int y = 0; y < 2; ++y) {
+                for (int y = 0; y < NY; ++y) {
                     const double2 bv = sb[kk][wb + 16 * y + lane % 16];
                     // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
                     acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, acc[x][y][0], 0, 0, 0);
@@ -167,17 +178,18 @@ __global__ __launch_bounds__(kT) void gram_kernel(const void *A, int nb_a, const
         }
         __syncthreads();
     }
-    // write the 64 x 64 partial tile (column-major inside the tile)
+    // write the partial tile into a 64 x 64 slot (column-major inside the slot;
+    // a BW = 32 tile fills its first 32 columns, the reduction reads no others)
     double2 *out = reinterpret_cast<double2 *>(part) +
                    ((int64_t)split * gridDim.x + tile) * (kGT * kGT);
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < NY; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ra = wa + 16 * x + lane / 16 + 4 * r;  // row of S (column of A)
-                const int cb = wb + 16 * y + lane % 16;            // column of S
+                const int cb = wb + 16 * y + lane % 16;            // column of S within the tile
                 double2 v;
                 v.x = acc[x][y][0][r];
                 v.y = acc[x][y][1][r];
@@ -217,44 +229,50 @@ __global__ __launch_bounds__(kT) void gram_reduce_kernel(const double *part, int
 // ---------------------------------------------------------------------------
 // Element types TA of A and TZ of Z (double: c128, float: c64) are template
 // parameters, as for the Gram product.
-template <typename TA, typename TZ>
+template <typename TA, typename TZ, int BW>
 __global__ __launch_bounds__(kT) void update_kernel(const void *A, int nb_a, const double *M, int ldm, void *Z,
                                                     int nb_z, int64_t n, int m1, int m2) {
+    // output tile 64 rows x BW columns of Z (BW = 32 when Z has at most 32 columns)
+    constexpr int NY = BW / 32;                // 16-column MFMA tiles per wave
     using RA = typename std::conditional<std::is_same<TA, double>::value, double2, float2>::type;
     using RZ = typename std::conditional<std::is_same<TZ, double>::value, double2, float2>::type;
     __shared__ double2 sa[kGT][kGK + 1];
-    __shared__ double2 sm[kGK][kGT];
+    __shared__ double2 sm[kGK][BW];
     const int64_t i0 = (int64_t)blockIdx.x * kGT;
-    const int c0 = blockIdx.y * kGT;
+    const int c0 = blockIdx.y * BW;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int wi = (wv & 1) * 32, wc = (wv >> 1) * 32;
+    const int wi = (wv & 1) * 32, wc = (wv >> 1) * (BW / 2);
     const double2 *Mc = reinterpret_cast<const double2 *>(M);
 
     // two accumulators per 16 x 16 tile: real and imaginary part of the sum
-    d4v acc[2][2][2];
+    d4v acc[2][NY][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < NY; ++y)
 #pragma unroll
             for (int q = 0; q < 2; ++q) acc[x][y][q] = d4v{0.0, 0.0, 0.0, 0.0};
 
-    // stages of kGK columns of A (64 rows) and kGK rows of M (64 columns): the next
+    // stages of kGK columns of A (64 rows) and kGK rows of M (BW columns): the next
     // stage's global loads are issued before the current stage's products
-    constexpr int kPer = kGT * kGK / kT;   // elements per thread and operand
-    RA pa[kPer];
-    double2 pm[kPer];
+    constexpr int kPerA = kGT * kGK / kT, kPerM = BW * kGK / kT;   // elements per thread
+    RA pa[kPerA];
+    double2 pm[kPerM];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < kPerA; ++q) {
             const int t = threadIdx.x + q * kT;
             const int rr = t / kGK, kk = t % kGK;
             const int64_t i = i0 + rr;
             RA va{};
             if (i < n && k0 + kk < m1) va = static_cast<const RA *>(A)[blocked_index(n, nb_a, i, k0 + kk)];
             pa[q] = va;
-            const int km = t / kGT, cc = t % kGT;
+        }
+#pragma unroll
+        for (int q = 0; q < kPerM; ++q) {
+            const int t = threadIdx.x + q * kT;
+            const int km = t / BW, cc = t % BW;
             double2 vm{0.0, 0.0};
             if (k0 + km < m1 && c0 + cc < m2) vm = Mc[(int64_t)(c0 + cc) * ldm + k0 + km];
             pm[q] = vm;
@@ -263,10 +281,14 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int nb_a, con
     fetch(0);
     for (int k0 = 0; k0 < m1; k0 += kGK) {
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < kPerA; ++q) {
             const int t = threadIdx.x + q * kT;
             sa[t / kGK][t % kGK] = double2{(double)pa[q].x, (double)pa[q].y};
-            sm[t / kGT][t % kGT] = pm[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kPerM; ++q) {
+            const int t = threadIdx.x + q * kT;
+            sm[t / BW][t % BW] = pm[q];
         }
         __syncthreads();
         if (k0 + kGK < m1) fetch(k0 + kGK);
@@ -277,7 +299,7 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int nb_a, con
             for (int x = 0; x < 2; ++x) {
                 const double2 av = sa[wi + 16 * x + lane % 16][kk];
 #pragma unroll
-                for (int y = 0; y < 2; ++y) {
+                for (int y = 0; y < NY; ++y) {
                     const double2 mv = sm[kk][wc + 16 * y + lane % 16];
                     // a m = (ar mr - ai mi) + i (ar mi + ai mr)
                     acc[x][y][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, mv.x, acc[x][y][0], 0, 0, 0);
@@ -292,7 +314,7 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int nb_a, con
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < NY; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = i0 + wi + 16 * x + lane / 16 + 4 * r;
@@ -715,18 +737,26 @@ int launch_gram(const void *A, int prec_a, int nb_a, const void *B, int prec_b, 
     const int64_t rps = ((n + nsplit - 1) / nsplit + 2 * kGK - 1) / (2 * kGK) * (2 * kGK);
     const dim3 grid(ntiles, nsplit);
     const bool a64 = prec_a == CHEBFD_PREC_FP64, b64 = prec_b == CHEBFD_PREC_FP64;
+    // at most 32 columns of B: 64 x 32 output tiles (the slots and the reduction stay 64 x 64)
+    const bool narrow = !herm && m2 <= 32;
+#define CHEBFD_GRAM(TA_, TB_)                                                                              \
+    do {                                                                                                   \
+        if (narrow)                                                                                        \
+            hipLaunchKernelGGL((gram_kernel<TA_, TB_, 32>), grid, dim3(kT), 0, s, A, nb_a, B, nb_b, n, m1, \
+                               m2, ta, herm, rps, part);                                                   \
+        else                                                                                               \
+            hipLaunchKernelGGL((gram_kernel<TA_, TB_, 64>), grid, dim3(kT), 0, s, A, nb_a, B, nb_b, n, m1, \
+                               m2, ta, herm, rps, part);                                                   \
+    } while (0)
     if (a64 && b64)
-        hipLaunchKernelGGL((gram_kernel<double, double>), grid, dim3(kT), 0, s, A, nb_a, B, nb_b, n, m1, m2, ta,
-                           herm, rps, part);
+        CHEBFD_GRAM(double, double);
     else if (a64)
-        hipLaunchKernelGGL((gram_kernel<double, float>), grid, dim3(kT), 0, s, A, nb_a, B, nb_b, n, m1, m2, ta,
-                           herm, rps, part);
+        CHEBFD_GRAM(double, float);
     else if (b64)
-        hipLaunchKernelGGL((gram_kernel<float, double>), grid, dim3(kT), 0, s, A, nb_a, B, nb_b, n, m1, m2, ta,
-                           herm, rps, part);
+        CHEBFD_GRAM(float, double);
     else
-        hipLaunchKernelGGL((gram_kernel<float, float>), grid, dim3(kT), 0, s, A, nb_a, B, nb_b, n, m1, m2, ta,
-                           herm, rps, part);
+        CHEBFD_GRAM(float, float);
+#undef CHEBFD_GRAM
     CHEBFD_HIP(hipGetLastError());
     const int64_t total = (int64_t)ntiles * kGT * kGT;
     int G = static_cast<int>((total + kT - 1) / kT);
@@ -745,20 +775,28 @@ size_t gram_part_bytes(int m1, int m2, int nsplit) {
 int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm, void *Z, int prec_z,
                   int nb_z, int64_t n, int m1, int m2, hipStream_t s) {
     if (!pow2(nb_a) || !pow2(nb_z)) CHEBFD_FAIL(CHEBFD_EINVAL, "block widths %d, %d must be powers of two", nb_a, nb_z);
-    const dim3 grid(static_cast<unsigned>((n + kGT - 1) / kGT), (m2 + kGT - 1) / kGT);
+    // at most 32 columns of Z: 64 x 32 output tiles
+    const int bw = m2 <= 32 ? 32 : kGT;
+    const dim3 grid(static_cast<unsigned>((n + kGT - 1) / kGT), (m2 + bw - 1) / bw);
     const bool a64 = prec_a == CHEBFD_PREC_FP64, z64 = prec_z == CHEBFD_PREC_FP64;
+#define CHEBFD_UPD(TA_, TZ_)                                                                                     \
+    do {                                                                                                         \
+        if (bw == 32)                                                                                            \
+            hipLaunchKernelGGL((update_kernel<TA_, TZ_, 32>), grid, dim3(kT), 0, s, A, nb_a, M, ldm, Z, nb_z, n, \
+                               m1, m2);                                                                          \
+        else                                                                                                     \
+            hipLaunchKernelGGL((update_kernel<TA_, TZ_, 64>), grid, dim3(kT), 0, s, A, nb_a, M, ldm, Z, nb_z, n, \
+                               m1, m2);                                                                          \
+    } while (0)
     if (a64 && z64)
-        hipLaunchKernelGGL((update_kernel<double, double>), grid, dim3(kT), 0, s, A, nb_a, M, ldm, Z, nb_z, n, m1,
-                           m2);
+        CHEBFD_UPD(double, double);
     else if (a64)
-        hipLaunchKernelGGL((update_kernel<double, float>), grid, dim3(kT), 0, s, A, nb_a, M, ldm, Z, nb_z, n, m1,
-                           m2);
+        CHEBFD_UPD(double, float);
     else if (z64)
-        hipLaunchKernelGGL((update_kernel<float, double>), grid, dim3(kT), 0, s, A, nb_a, M, ldm, Z, nb_z, n, m1,
-                           m2);
+        CHEBFD_UPD(float, double);
     else
-        hipLaunchKernelGGL((update_kernel<float, float>), grid, dim3(kT), 0, s, A, nb_a, M, ldm, Z, nb_z, n, m1,
-                           m2);
+        CHEBFD_UPD(float, float);
+#undef CHEBFD_UPD
     CHEBFD_HIP(hipGetLastError());
     return CHEBFD_OK;
 }
