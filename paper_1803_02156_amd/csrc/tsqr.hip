@@ -15,8 +15,9 @@
 //     owns column j holds rows l, l + 32, ..., l + 224 of it in lane l's
 //     registers; per Householder step the owner of the pivot column puts its
 //     reflector in LDS and the other columns form their products with it by a
-//     32-lane shuffle reduction (one barrier per step); the node's explicit Q
-//     is then formed in place from its reflectors.  The leaves are the 256-row
+//     32-lane sum (DPP within rows of 16 lanes, one permute across; one barrier
+//     per step); the node's explicit Q is then formed in place from its
+//     reflectors.  The leaves are the 256-row
 //     ranges of T; a node of the next level stacks the R factors of 256 / PW
 //     children.  The root's R is the panel's diagonal block of R after a phase
 //     per column makes its diagonal real positive (the phase goes into Q);
@@ -61,11 +62,25 @@ __device__ inline void st_c(void *base, int prec, int64_t idx, double2 v) {
     }
 }
 
-// sum over the 32 lanes of a half-wave; every lane gets the same value
-// (each butterfly stage adds the same two operands in every lane)
+// lane permutation within rows of 16 lanes by DPP (no LDS round trip)
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// sum over the 32 lanes of a half-wave; every lane gets the same value (each
+// stage adds a lane's value and its partner's, and a + b == b + a exactly).
+// Partners: xor 1 and xor 2 within a quad, then lane i and 7 - i within eight
+// lanes, then i and 15 - i within sixteen (DPP), then xor 16 (a permute).
 __device__ inline double sum32(double v) {
-#pragma unroll
-    for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
+    v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    v += __shfl_xor(v, 16, 32);
     return v;
 }
 
