@@ -229,9 +229,12 @@ __global__ __launch_bounds__(kT) void gram_reduce_kernel(const double *part, int
 // ---------------------------------------------------------------------------
 // Element types TA of A and TZ of Z (double: c128, float: c64) are template
 // parameters, as for the Gram product.
-template <typename TA, typename TZ, int BW>
+// Z = A M, or Z = S - A M when TS (the storage type of S, blocked width nb_s) is
+// not void; S may be Z itself (each entry is read by the thread that writes it).
+template <typename TA, typename TZ, int BW, typename TS = void>
 __global__ __launch_bounds__(kT) void update_kernel(const void *A, int nb_a, const double *M, int ldm, void *Z,
-                                                    int nb_z, int64_t n, int m1, int m2) {
+                                                    int nb_z, int64_t n, int m1, int m2, const void *S = nullptr,
+                                                    int nb_s = 1) {
     // output tile 64 rows x BW columns of Z (BW = 32 when Z has at most 32 columns)
     constexpr int NY = BW / 32;                // 16-column MFMA tiles per wave
     using RA = typename std::conditional<std::is_same<TA, double>::value, double2, float2>::type;
@@ -320,9 +323,16 @@ __global__ __launch_bounds__(kT) void update_kernel(const void *A, int nb_a, con
                 const int64_t i = i0 + wi + 16 * x + lane / 16 + 4 * r;
                 const int c = c0 + wc + 16 * y + lane % 16;
                 if (i < n && c < m2) {
+                    double vx = acc[x][y][0][r], vy = acc[x][y][1][r];
+                    if constexpr (!std::is_void<TS>::value) {
+                        using RS = typename std::conditional<std::is_same<TS, double>::value, double2, float2>::type;
+                        const RS sv = static_cast<const RS *>(S)[blocked_index(n, nb_s, i, c)];
+                        vx = static_cast<double>(sv.x) - vx;
+                        vy = static_cast<double>(sv.y) - vy;
+                    }
                     RZ v;
-                    v.x = static_cast<TZ>(acc[x][y][0][r]);
-                    v.y = static_cast<TZ>(acc[x][y][1][r]);
+                    v.x = static_cast<TZ>(vx);
+                    v.y = static_cast<TZ>(vy);
                     static_cast<RZ *>(Z)[blocked_index(n, nb_z, i, c)] = v;
                 }
             }
@@ -797,6 +807,29 @@ int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm,
     else
         CHEBFD_UPD(float, float);
 #undef CHEBFD_UPD
+    CHEBFD_HIP(hipGetLastError());
+    return CHEBFD_OK;
+}
+
+int launch_update_sub(const void *A, int prec_a, int nb_a, const double *M, int ldm, const void *S, int prec_s,
+                      int nb_s, double *Z, int nb_z, int64_t n, int m1, int m2, hipStream_t s) {
+    if (!pow2(nb_a) || !pow2(nb_z) || !pow2(nb_s))
+        CHEBFD_FAIL(CHEBFD_EINVAL, "block widths %d, %d, %d must be powers of two", nb_a, nb_s, nb_z);
+    if (m2 > 32) CHEBFD_FAIL(CHEBFD_EINVAL, "Z = S - A M takes at most 32 columns (%d)", m2);
+    const dim3 grid(static_cast<unsigned>((n + kGT - 1) / kGT), 1);
+    const bool a64 = prec_a == CHEBFD_PREC_FP64, s64 = prec_s == CHEBFD_PREC_FP64;
+#define CHEBFD_UPDS(TA_, TS_)                                                                                  \
+    hipLaunchKernelGGL((update_kernel<TA_, double, 32, TS_>), grid, dim3(kT), 0, s, A, nb_a, M, ldm,          \
+                       static_cast<void *>(Z), nb_z, n, m1, m2, S, nb_s)
+    if (a64 && s64)
+        CHEBFD_UPDS(double, double);
+    else if (a64)
+        CHEBFD_UPDS(double, float);
+    else if (s64)
+        CHEBFD_UPDS(float, double);
+    else
+        CHEBFD_UPDS(float, float);
+#undef CHEBFD_UPDS
     CHEBFD_HIP(hipGetLastError());
     return CHEBFD_OK;
 }

@@ -117,6 +117,10 @@ inline int gram_splits(int64_t n, int m1, int m2) {
 }
 int launch_update(const void *A, int prec_a, int nb_a, const double *M, int ldm, void *Z, int prec_z,
                   int nb_z, int64_t n, int m1, int m2, hipStream_t s);
+// Z = S - A M (Z FP64, at most 32 columns, blocked width nb_z; S of precision
+// prec_s, blocked width nb_s, may alias Z)
+int launch_update_sub(const void *A, int prec_a, int nb_a, const double *M, int ldm, const void *S, int prec_s,
+                      int nb_s, double *Z, int nb_z, int64_t n, int m1, int m2, hipStream_t s);
 // Jacobi eigensolver (host-driven sweeps, one launch per round); synchronises `s`
 // once per sweep to read the off-diagonal norm
 size_t jacobi_scratch_bytes(int m);
@@ -141,11 +145,11 @@ int launch_fix_phases(void *Z, int prec, int64_t n, int nb, int m, double *phase
 // TSQR (tsqr.hip): Y (n x m, blocked width nb, prec_y) = Q R, Q into a second
 // block vector (prec_q, same nb), R (m x m, FP64 complex, column-major, ldr)
 // upper triangular with a real non-negative diagonal.  Panels of
-// tsqr_panel_width(nb) columns; work buffers: T and U (n x panel width FP64
-// complex each), tree (tsqr_tree_bytes), C1 and C2 (m x panel width, leading
+// tsqr_panel_width(nb) columns; work buffers: T (n x panel width FP64
+// complex), tree (tsqr_tree_bytes), C1 and C2 (m x panel width, leading
 // dimension ldc >= m) and gpart (tsqr_gpart_bytes).
 struct TsqrWork {
-    double *T, *U, *tree, *C1, *C2;
+    double *T, *tree, *C1, *C2;
     int ldc;
     double *gpart;
 };

@@ -182,7 +182,7 @@ int chebfd_tsqr_query(int64_t n, int32_t m, int32_t n_b, size_t *work_bytes) {
                    (long long)n, m);
     CHEBFD_REQUIRE(n_b >= 1 && n_b <= 128 && (n_b & (n_b - 1)) == 0, "n_b = %d invalid", n_b);
     const size_t pw = tsqr_panel_width(n_b);
-    *work_bytes = 2 * al((size_t)n * pw * 16) + al(tsqr_tree_bytes(n, (int)pw)) + 2 * al((size_t)m * pw * 16) +
+    *work_bytes = al((size_t)n * pw * 16) + al(tsqr_tree_bytes(n, (int)pw)) + 2 * al((size_t)m * pw * 16) +
                   al(tsqr_gpart_bytes(n, m, n_b));
     return CHEBFD_OK;
 }
@@ -207,7 +207,6 @@ int chebfd_tsqr(int64_t n, int32_t m, int32_t n_b, int32_t prec, const void *d_y
     auto take = [&](size_t bytes) { double *h = reinterpret_cast<double *>(base + at); at += al(bytes); return h; };
     TsqrWork w;
     w.T = take((size_t)n * pw * 16);
-    w.U = take((size_t)n * pw * 16);
     w.tree = take(tsqr_tree_bytes(n, (int)pw));
     w.C1 = take((size_t)m * pw * 16);
     w.C2 = take((size_t)m * pw * 16);
@@ -353,7 +352,7 @@ int chebfd_solve(const chebfd_matrix *H, const chebfd_matrix *H64, const chebfd_
     std::vector<double> hinfo(2 * (size_t)ns), hsel;
     auto orth_tsqr = [&](Stage &g, int *k) -> int {
         int r;
-        const TsqrWork w{DD(L.b64), DD(L.t64), DD(L.tree), DD(L.V), DD(L.G), ns, DD(L.gpart)};
+        const TsqrWork w{DD(L.b64), DD(L.tree), DD(L.V), DD(L.G), ns, DD(L.gpart)};
         if ((r = tsqr_blocked(n, g.ns, g.nb, g.prec, g.X, g.prec, g.Q, DD(L.S), ns, w, s))) return r;
         if ((r = launch_tsqr_colinfo(g.ns, DD(L.S), ns, DD(L.T), s))) return r;
         CHEBFD_HIP(hipMemcpyAsync(hinfo.data(), DD(L.T), sizeof(double) * 2 * g.ns, hipMemcpyDeviceToHost, s));

@@ -298,19 +298,6 @@ __global__ __launch_bounds__(apply_threads(PW)) void tsqr_apply_kernel(const dou
     }
 }
 
-// T(i, c) = src(i, c) - U(i, c) for c < cols; T and U FP64 with row stride pw
-__global__ __launch_bounds__(kEw) void tsqr_sub_kernel(const void *src, int prec, int64_t ld, const double2 *U,
-                                                       double2 *T, int64_t n, int pw, int cols) {
-    const int64_t total = n * pw;
-    for (int64_t t = (int64_t)blockIdx.x * kEw + threadIdx.x; t < total; t += (int64_t)gridDim.x * kEw) {
-        const int64_t i = t / pw;
-        const int c = static_cast<int>(t % pw);
-        if (c >= cols) continue;
-        const double2 y = ld_c(src, prec, i * ld + c), u = U[t];
-        T[t] = double2{y.x - u.x, y.y - u.y};
-    }
-}
-
 // Off-diagonal blocks of the panel's columns c0 .. c0 + cols - 1 of R:
 // rows < c0 get C1 + C2 (the two projections; absent for the first panel),
 // rows >= c0 + cols get zero.
@@ -440,7 +427,7 @@ int tsqr_blocked(int64_t n, int m, int nb, int prec_y, const void *Y, int prec_q
                  const TsqrWork &w, hipStream_t s) {
     const int pw = tsqr_panel_width(nb);
     const size_t ey = vec_elem_bytes(prec_y), eq = vec_elem_bytes(prec_q);
-    double2 *T = reinterpret_cast<double2 *>(w.T), *U = reinterpret_cast<double2 *>(w.U);
+    double2 *T = reinterpret_cast<double2 *>(w.T);
     double2 *R2 = reinterpret_cast<double2 *>(R);
     int r;
     for (int c0 = 0; c0 < m; c0 += pw) {
@@ -456,17 +443,16 @@ int tsqr_blocked(int64_t n, int m, int nb, int prec_y, const void *Y, int prec_q
             const int splits = gram_splits(n, c0, cols);
             if ((r = launch_gram(Q, prec_q, nb, ysrc, prec_y, nb, n, c0, cols, w.gpart, splits, w.C1, w.ldc, s)))
                 return r;
-            if ((r = launch_update(Q, prec_q, nb, w.C1, w.ldc, U, CHEBFD_PREC_FP64, pw, n, c0, cols, s))) return r;
-            hipLaunchKernelGGL(tsqr_sub_kernel, dim3(ew_grid(n * pw)), dim3(kEw), 0, s, ysrc, prec_y, (int64_t)nb,
-                               U, T, n, pw, cols);
-            CHEBFD_HIP(hipGetLastError());
+            // T = Y - Q C1, then T = T - Q C2 (the subtraction in the update's epilogue)
+            if ((r = launch_update_sub(Q, prec_q, nb, w.C1, w.ldc, ysrc, prec_y, nb, reinterpret_cast<double *>(T), pw,
+                                       n, c0, cols, s)))
+                return r;
             if ((r = launch_gram(Q, prec_q, nb, T, CHEBFD_PREC_FP64, pw, n, c0, cols, w.gpart, splits, w.C2, w.ldc,
                                  s)))
                 return r;
-            if ((r = launch_update(Q, prec_q, nb, w.C2, w.ldc, U, CHEBFD_PREC_FP64, pw, n, c0, cols, s))) return r;
-            hipLaunchKernelGGL(tsqr_sub_kernel, dim3(ew_grid(n * pw)), dim3(kEw), 0, s, T, (int)CHEBFD_PREC_FP64,
-                               (int64_t)pw, U, T, n, pw, cols);
-            CHEBFD_HIP(hipGetLastError());
+            if ((r = launch_update_sub(Q, prec_q, nb, w.C2, w.ldc, T, CHEBFD_PREC_FP64, pw,
+                                       reinterpret_cast<double *>(T), pw, n, c0, cols, s)))
+                return r;
             src = T;
             prec_src = CHEBFD_PREC_FP64;
             ld_src = pw;

@@ -137,18 +137,18 @@ def test_mlp_query_sizes(lib):
 
 
 def test_tsqr_query_host(lib):
-    """Workspace of chebfd_tsqr: two FP64 panels, the reduction tree (one level above
+    """Workspace of chebfd_tsqr: one FP64 panel, the reduction tree (one level above
     the leaves per factor 256 / panel width), the projections and the Gram partials;
     invalid sizes are rejected before any device work."""
     sz = ctypes.c_size_t()
     assert lib.chebfd_tsqr_query(256, 32, 32, ctypes.byref(sz)) == 0
     single = sz.value                      # one leaf: no tree, no projection
-    assert single >= 2 * 256 * 32 * 16
+    assert single >= 256 * 32 * 16 + 2 * 32 * 32 * 16     # panel T, projections C1, C2
     assert lib.chebfd_tsqr_query(70000, 96, 32, ctypes.byref(sz)) == 0
     big = sz.value
-    # panels T, U (n x 32 x 16 B) plus tree levels of 274 x 32, 35 x 32, 5 x 32 rows
+    # panel T (n x 32 x 16 B) plus tree levels of 274 x 32, 35 x 32, 5 x 32 rows
     tree = sum(-(-rows * 32 * 16 // 256) * 256 for rows in (274 * 32, 35 * 32, 5 * 32))
-    assert big >= 2 * 70000 * 32 * 16 + tree
+    assert big >= 70000 * 32 * 16 + tree
     assert lib.chebfd_tsqr_query(10, 11, 4, ctypes.byref(sz)) < 0      # m > n
     assert lib.chebfd_tsqr_query(100, 10, 3, ctypes.byref(sz)) < 0     # n_b not a power of two
     assert lib.chebfd_tsqr_query(100000, 5000, 32, ctypes.byref(sz)) < 0   # m > 4096
