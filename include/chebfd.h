@@ -187,8 +187,8 @@ int chebfd_filter_query(const chebfd_matrix *H, int32_t n_b, size_t *work_bytes)
  * what they stage in LDS):
  *   CHEBFD_KERNEL_WINDOW   one workgroup per CU sweeps a contiguous row range and
  *                          gathers U from a window of U rows staged in LDS (FP64
- *                          n_b = 32, c64 n_b = 64, and c64 n_b = 32 on large
- *                          matrices; C = 32; rows of at most 13 entries;
+ *                          n_b = 32, c64 n_b = 64, and c64 n_b = 32 from 32
+ *                          tiles of 64 rows per CU on; C = 32; rows of at most 13 entries;
  *                          window_local[] >= 700 for the tile height); the
  *                          ranges of one XCD are held within a few tiles of
  *                          each other through progress words in the workspace

@@ -312,17 +312,18 @@ int chebfd_matrix_build(int64_t n, const int64_t *h_rowptr, const int32_t *h_col
     m.uniform_width = p.max_width;
     for (int64_t c = 0; c < p.n_chunks; ++c)
         if (p.width[c] != p.max_width) { m.uniform_width = 0; break; }
-    // locality of the gathers: entries whose column lies within kWinHalo tiles
-    // of their row's tile (tiles of 32 and 64 rows)
+    // locality of the gathers: entries whose column lies within the window
+    // kernel's halo of their row's tile (tiles of 32 and 64 rows)
     for (int v = 0; v < 2; ++v) {
         const int64_t tr = 32 << v;
+        const int64_t halo = win_halo(static_cast<int>(tr));
         int64_t local = 0;
         for (int64_t i = 0; i < n; ++i) {
             const int64_t t0 = i / tr * tr;
             const int32_t old = p.perm[i];
             for (int64_t k = h_rowptr[old]; k < h_rowptr[old + 1]; ++k) {
                 const int64_t q = iperm[h_col[k]];
-                local += (q >= t0 - kWinHalo * tr && q < t0 + (kWinHalo + 1) * tr) ? 1 : 0;
+                local += (q >= t0 - halo * tr && q < t0 + (halo + 1) * tr) ? 1 : 0;
             }
         }
         m.window_local[v] = nnz > 0 ? static_cast<int32_t>(local * 1000 / nnz) : 1000;

@@ -11,9 +11,10 @@
 // contiguous range of tiles and keeps a window of U in LDS: a ring of
 // kWinBlocks blocks of TR rows (TR = rows of one tile, 16 KB per block).
 // While tile t (rows [t TR, t TR + TR)) is processed the ring holds blocks
-// t - kWinHalo .. t + kWinHalo and receives block t + kWinHalo + 1, which is
-// loaded from HBM once (coalesced, one 16-byte access per thread) and read by
-// the next 2 kWinHalo + 1 tiles.  Gathers inside the window are LDS reads;
+// t - h .. t + h (h = win_halo(TR): 3 tiles of 32 rows, 1 tile of 64) and
+// receives block t + h + 1, which is loaded from HBM once (coalesced, one
+// 16-byte access per thread) and read by the next 2 h + 1 tiles.  Gathers
+// inside the window are LDS reads;
 // columns outside it are gathered from global memory as before.  The vector
 // memory pipeline then carries about one U access per row instead of one per
 // stored entry, plus the streams of W and Y (non-temporal) and the matrix
@@ -54,6 +55,8 @@ struct WinShape {
     static constexpr int TR = kWinThreads / LPR;       // rows per tile (one per lane group)
     static constexpr int RB = NB * 2 * sizeof(T);      // bytes of one row of U
     static constexpr int RING_ROWS = kWinBlocks * TR;  // power of two
+    static constexpr int HALO = win_halo(TR);          // window: tiles t - HALO .. t + HALO
+    static_assert(2 * HALO + 2 <= kWinBlocks, "the window and the incoming block fit the ring");
     static constexpr int CPT = TR / 32;                // SELL chunks (C = 32) per tile
 };
 
@@ -119,6 +122,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
     using PK = Pack<T, S::CPL>;
     constexpr int CPL = S::CPL, LPR = S::LPR, TR = S::TR, RB = S::RB;
     constexpr int CPT = S::CPT;
+    constexpr int HALO = S::HALO;
     constexpr int O_MAT = S::RING_ROWS * RB;
     static_assert(win_supported<T, NB>(), "tile shape does not fit the window kernel");
     static_assert(MB::SLOTS <= kWinThreads, "one matrix slot per thread and tile");
@@ -218,16 +222,16 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
     // (the reduction above ends with a barrier: the ring area is free)
     if (tb < te) {
         // prologue: the window of the first tile and its matrix slots
-        PK pro[2 * kWinHalo + 1];
+        PK pro[2 * HALO + 1];
 #pragma unroll
-        for (int q = 0; q < 2 * kWinHalo + 1; ++q) {
-            const int blk = tb - kWinHalo + q;
+        for (int q = 0; q < 2 * HALO + 1; ++q) {
+            const int blk = tb - HALO + q;
             if (row_ok(blk)) pro[q] = load_pack<T, CPL, false>(P + 2 * ((int64_t)(blk * TR + rr) * NB + jc));
         }
         fetch_mat(tb);
 #pragma unroll
-        for (int q = 0; q < 2 * kWinHalo + 1; ++q) {
-            const int blk = tb - kWinHalo + q;
+        for (int q = 0; q < 2 * HALO + 1; ++q) {
+            const int blk = tb - HALO + q;
             if (row_ok(blk)) ring_store(blk, pro[q]);
         }
         deposit_mat(tb, 0);
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
         const int t0 = tile * TR;
         const int i = t0 + rr;
         const bool live = FULL || i < n32;
-        const int wlo = t0 - kWinHalo * TR;   // window [wlo, wlo + (2 kWinHalo + 1) TR)
+        const int wlo = t0 - HALO * TR;   // window [wlo, wlo + (2 HALO + 1) TR)
         const VT *sv = CHEBFD_WV(buf);
         const int32_t *sc = CHEBFD_WC(buf);
 
@@ -278,13 +282,13 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
         if (live) {
 #pragma unroll
             for (int k = 0; k < MAXW; ++k) {
-                inw[k] = static_cast<unsigned>(cc[k] - wlo) < static_cast<unsigned>((2 * kWinHalo + 1) * TR);
+                inw[k] = static_cast<unsigned>(cc[k] - wlo) < static_cast<unsigned>((2 * HALO + 1) * TR);
                 if (!inw[k]) u[k] = load_pack<T, CPL, false>(P + 2 * ((int64_t)cc[k] * NB + jc));
             }
         }
         // prefetches: next tile's matrix slots, W and Y rows; the block entering the window
         PK rf;
-        const int nb_in = tile + kWinHalo + 1;
+        const int nb_in = tile + HALO + 1;
         const bool ring_in = more && row_ok(nb_in);
         if (ring_in) rf = load_pack<T, CPL, false>(P + 2 * ((int64_t)(nb_in * TR + rr) * NB + jc));
         if (more) fetch_mat(tile + 1);
@@ -370,7 +374,7 @@ __global__ __launch_bounds__(kWinThreads) void cheb_win_kernel(StepArgs a, int64
                 }
             }
         }
-        // block tile + kWinHalo + 1 replaces block tile - kWinHalo - 1 (outside
+        // block tile + HALO + 1 replaces block tile - HALO - 1 (outside
         // this tile's window); the next tile's slots go to the idle buffer.  Their
         // loads were issued before the W and Y loads and the stores, so the wait
         // for them leaves those in flight; the stores also stay in flight across
@@ -506,8 +510,8 @@ bool win_geometry(const chebfd_matrix *H, int prec, int nb, int num_cus, WinGeom
     if (H->C != 32 || H->max_width > kWinWidth) return false;
     int tr;
     // instances where the window beats the LDS-staged kernel (measured): FP64
-    // n_b = 32, c64 n_b = 64, and c64 n_b = 32 on large matrices (tiles of 64
-    // rows; with few tiles per workgroup the LDS-staged kernel is faster there)
+    // n_b = 32, c64 n_b = 64, and c64 n_b = 32 from 32 tiles of 64 rows per CU
+    // (the 64x64x32 lattice: 141 against 151 us per step)
     if (prec == CHEBFD_PREC_FP64 && nb == 32)
         tr = WinShape<double, 32>::TR;
     else if (prec == CHEBFD_PREC_MIXED && nb == 64)

@@ -65,15 +65,20 @@ int launch_lds_step(int prec, int nb, int mode, const StepArgs &a, const LdsGeom
                     hipStream_t s);
 // Window step kernel (filter_win.hip): one 1024-thread workgroup per CU sweeps
 // a contiguous range of tiles and gathers from a ring of U rows staged in LDS
-// (kWinBlocks blocks of one tile each; tile t reads blocks t - kWinHalo ..
-// t + kWinHalo).  Used for FP64 n_b = 32 and c64 n_b = 64, rows of at most
-// kWinWidth entries, when at least kWinMinLocal of 1000 stored entries fall
-// inside the window.
+// (kWinBlocks blocks of one tile each; tile t reads blocks t - h .. t + h,
+// h = win_halo(tile rows)).  Used for FP64 n_b = 32, c64 n_b = 64 and c64
+// n_b = 32, rows of at most kWinWidth entries, when at least kWinMinLocal of
+// 1000 stored entries fall inside the window.
 constexpr int kWinBlocks = 8;
-constexpr int kWinHalo = 3;
+// Window half-width in tiles: 3 tiles of 32 rows, 1 tile of 64 rows.  The
+// z-neighbours of 4 x 4 pencils (4 orbitals) lie 64 rows away; with 32-row
+// tiles a window of 2 tiles measured 7 % slower than 3, with 64-row tiles 1
+// tile beats 3 (fewer prologue blocks: 64x64x32 c64 n_b = 32 step 151.6 ->
+// 141.1 us).
+constexpr int win_halo(int tr) { return tr >= 64 ? 1 : 3; }
 constexpr int kWinWidth = 13;       // rows of at most this many stored entries
 constexpr int kWinMinLocal = 700;
-constexpr int kWinC64Nb32Tiles = 256;   // c64 n_b = 32 takes the window kernel from this many 64-row tiles per CU
+constexpr int kWinC64Nb32Tiles = 32;   // c64 n_b = 32 takes the window kernel from this many 64-row tiles per CU
 struct WinGeometry {
     int tr;             // rows per tile
     int uniform;        // 1: every chunk holds exactly kWinWidth slots per row

@@ -59,9 +59,11 @@ def _widened(lo, hi):
 
 
 # lattice, prec, n_b, n_p, kernel the library must pick (the benchmark's 64x64x32 matrix; c64
-# n_b = 32 on the 128x128x64 lattice, where it takes the window kernel)
+# n_b = 32 takes the window kernel with 64-row tiles and a one-tile halo, c64 n_b = 16 the
+# LDS-staged kernel)
 FULL_CASES = [((64, 64, 32), 0, 32, 60, "window"), ((64, 64, 32), 1, 64, 60, "window"),
-              ((64, 64, 32), 1, 32, 60, "lds"), ((128, 128, 64), 1, 32, 20, "window")]
+              ((64, 64, 32), 1, 32, 60, "window"), ((64, 64, 32), 1, 16, 60, "lds"),
+              ((128, 128, 64), 1, 32, 20, "window")]
 
 
 @pytest.mark.parametrize("dims,prec,n_b,n_p,kernel", FULL_CASES)
@@ -118,7 +120,7 @@ def _plane_wave(dims, j, v):
 
 BLOCH_CASES = [
     ((128, 128, 64), 0, 32, "window"),
-    ((128, 128, 64), 1, 32, "window"),     # c64 n_b = 32 takes the window kernel from 128x128x64 on
+    ((128, 128, 64), 1, 32, "window"),     # c64 n_b = 32: 64-row tiles, one-tile halo
     ((256, 256, 128), 0, 32, "window"),    # the largest single-GPU configuration, benchmark geometry
     ((256, 256, 128), 1, 32, "window"),
     ((256, 256, 128), 1, 64, "window"),

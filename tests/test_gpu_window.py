@@ -94,7 +94,8 @@ def test_window_filter_parity(P, dims, dil, pencil, sigma, prec, n_b, n_s, n_p):
 
 def test_window_locality_matches_definition(P):
     """window_local (entries per 1000 whose permuted column lies in
-    [t0 - 3 TR, t0 + 4 TR) for the tile start t0 of the permuted row) against
+    [t0 - h TR, t0 + (h + 1) TR) for the tile start t0 of the permuted row; the
+    window kernel's halo h is 3 tiles of 32 rows or 1 tile of 64 rows) against
     a recount from the CRS arrays and the handle's permutation."""
     dims = (8, 8, 8)
     H = topi_csr(*dims, m=1.0, W=1.0, seed=5, dilution=0.1, dilution_seed=3)
@@ -107,9 +108,9 @@ def test_window_locality_matches_definition(P):
     iperm[perm] = np.arange(n)
     rows = np.repeat(np.arange(n), np.diff(rowptr))
     pr, pc = iperm[rows], iperm[col]
-    for v, tr in enumerate((32, 64)):
+    for v, (tr, h) in enumerate(((32, 3), (64, 1))):
         t0 = pr // tr * tr
-        inside = np.count_nonzero((pc >= t0 - 3 * tr) & (pc < t0 + 4 * tr))
+        inside = np.count_nonzero((pc >= t0 - h * tr) & (pc < t0 + (h + 1) * tr))
         assert M.handle.window_local[v] == inside * 1000 // len(col)
 
 
