@@ -13,6 +13,9 @@
    known in closed form for every row, and every row's 13 gathers (all six
    neighbour blocks, across workgroup and XCD ranges) enter the result.
 
+3. The unfused filter (separate SpMMV, dot and axpby calls) against the oracle on
+   the same 64x64x32 matrix, FP64 and c64.
+
 Tolerances as in test_gpu_filter.py: p (nnzr + 4) u / sqrt(1 - s^2) for T_p x,
 times sum |gamma_p| for Y, times 2n for the dot products.
 """
@@ -91,6 +94,40 @@ def test_full_size_filter_matches_oracle(P, dims, prec, n_b, n_p, kernel):
     tol_Y = max(np.sum(np.abs(gam)), 1.0) * tol_T
     err_Y = np.max(np.abs(Y - Yr))
     tol_m = 2.0 * n * tol_T + n * 4 * u
+    err_e = np.max(np.abs(eta[1:] - etar[1:]))
+    err_n = np.max(np.abs(nu[1:] - nur[1:].real))
+    print(f"# max|Y - Y_oracle| {err_Y:.3e} (bound {tol_Y:.3e}), eta {err_e:.3e}, nu {err_n:.3e} "
+          f"(bound {tol_m:.3e})", flush=True)
+    assert err_Y <= tol_Y and err_e <= tol_m and err_n <= tol_m
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_unfused_matches_oracle(P, prec):
+    """The unfused filter (SpMMV, dot and axpby as separate calls, the paper's
+    fused-versus-unfused comparison of Sect. 3.2) at the benchmark matrix's size,
+    in the launch shapes of the full-size runs (dot products on the step kernel's
+    one-workgroup-per-CU grid, axpby over a flat grid of 16-byte vectors)."""
+    from paper_1803_02156_amd.ordering import lattice_row_order
+    dims, n_b, n_p = (64, 64, 32), 32, 40
+    print(f"\n# full-size unfused parity: {dims} lattice order, prec {prec}, n_b {n_b}", flush=True)
+    H = topi_csr(*dims, m=1.0, W=1.0, seed=1002)
+    n = len(H[0]) - 1
+    M = P.chebfd_matrix_build(*H, C=32, sigma=256, prec=prec, order=lattice_row_order(*dims))
+    lo, hi = P.chebfd_bounds(M)
+    lo2, hi2, s = _widened(lo, hi)
+    al, be, gam = P.chebfd_coefficients(lo2, hi2, -0.3, 0.2, n_p)
+    X = random_phase_block(n, n_b, 67)
+    xb = P.chebfd_pack(M, _to_dev_colmajor(X), n_b)
+    eta, nu = P.chebfd_filter_unfused(M, al, be, gam, n_b, n_b, xb)
+    Y = P.chebfd_unpack(M, xb).cpu().numpy()
+    eta, nu = eta.cpu().numpy(), nu.cpu().numpy()
+    del xb, M
+    Yr, etar, nur = O.chebyshev_filter(H, al, be, gam, X, n_b)
+    u = EPS64 if prec == 0 else EPS32
+    tol_T = _bound(n_p, 13, u, s)
+    tol_Y = max(np.sum(np.abs(gam)), 1.0) * tol_T
+    tol_m = 2.0 * n * tol_T + n * 4 * u
+    err_Y = np.max(np.abs(Y - Yr))
     err_e = np.max(np.abs(eta[1:] - etar[1:]))
     err_n = np.max(np.abs(nu[1:] - nur[1:].real))
     print(f"# max|Y - Y_oracle| {err_Y:.3e} (bound {tol_Y:.3e}), eta {err_e:.3e}, nu {err_n:.3e} "
