@@ -116,3 +116,35 @@ def test_grouped_sweeps_take_neighbour_pencils_together():
     finally:
         O.pencil_groups = saved
     assert grouped < 0.75 * plain, (grouped, plain)
+
+
+@pytest.mark.parametrize("dims", [(64, 64, 32), (128, 128, 64)])
+def test_window_halo_holds_the_lattice_neighbours(dims):
+    """The window step kernel reads a gathered row from LDS when its permuted index
+    lies within h tiles of the row's tile: h = 3 for 32-row tiles, h = 1 for
+    64-row tiles.  In the default lattice order (4 x 4 pencils of 4 orbitals,
+    z-neighbours 64 rows apart) both windows must hold at least 700 of 1000
+    entries of a Topi row (the kernel's selection threshold), and the one-tile
+    window of 64-row tiles as many as the three-tile window of 32-row tiles:
+    every z-neighbour is inside, only x/y-neighbours in other pencils are not."""
+    from topi import topi_csr
+    Nx, Ny, Nz = dims
+    rowptr, col, _ = topi_csr(Nx, Ny, Nz, m=1.0, W=1.0, seed=1)
+    o = lattice_row_order(Nx, Ny, Nz)
+    iperm = np.empty(o.size, dtype=np.int64)
+    iperm[o] = np.arange(o.size)
+    rows = np.repeat(np.arange(o.size), np.diff(rowptr))
+    pr, pc = iperm[rows], iperm[col]
+    share = {}
+    for tr, h in ((32, 3), (64, 1)):
+        t0 = pr // tr * tr
+        share[tr] = np.count_nonzero((pc >= t0 - h * tr) & (pc < t0 + (h + 1) * tr)) * 1000 // len(col)
+        assert share[tr] >= 700, (tr, share[tr])
+    assert share[64] >= share[32] - 5, share
+    # z-neighbours (4 x 4 x 4 = 64 rows apart in a pencil) are always inside the 64-row window
+    s = np.arange(Nx * Ny * Nz)
+    x, y, z = s % Nx, (s // Nx) % Ny, s // (Nx * Ny)
+    zn = x + Nx * (y + Ny * ((z + 1) % Nz))
+    same_box = (z + 1) % (Nz // 2 if Nz % 2 == 0 else Nz) != 0
+    d = np.abs(iperm[4 * zn] // 64 - iperm[4 * s] // 64)
+    assert np.all(d[same_box] <= 1)
